@@ -1,0 +1,83 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module draws random numbers and lays out test inputs. It holds none of
+the method's arithmetic: no wavelet filter, no extension map, no blur, no
+solver step. Blurred observations b are formed by whichever side is under test
+(the oracle in tests, the GPU library in the benchmark), from the clean image
+and the noise drawn here.
+
+Workload recipe (stand-in for the resolution test chart of the deblurring
+experiment, Sec. "The adjoint for orthogonal wavelets", and for the acoustic
+data of the blind channel example, Sec. "Example 2"; neither data set is
+available):
+
+* ``gen_image``: background 0; 20 axis-aligned rectangles, each with sorted
+  random corners and a U[0,1] intensity, painted in order (later ones overwrite
+  earlier ones); plus a linear gradient gu*u + gv*v with u, v in [0,1] and
+  gu, gv ~ U[-0.25, 0.25]; clipped to [0,1].
+* ``gen_noise``: i.i.d. N(0, sigma^2), sigma = 1e-3 by default.
+* ``gen_conv_pair``: h ~ N(0,1) of length K, s ~ N(0,1) of length N.
+* ``gen_batched_config``: the uneven batch (image sides drawn from
+  {512, 768, ..., 4096} independently per axis, levels from {3,4,5}, filters
+  from {Haar, Daubechies-4, Daubechies-8}, PSF sigma ~ U[1,4], radius
+  ceil(3 sigma)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def rng_for(config_id: int, index: int) -> np.random.Generator:
+    """One independent stream per (workload id, item index)."""
+    return np.random.default_rng((int(config_id), int(index)))
+
+
+def gen_image(rng: np.random.Generator, rows: int, cols: int, n_rect: int = 20) -> np.ndarray:
+    """Piecewise-constant rectangles plus a linear gradient, float64 in [0,1]."""
+    img = np.zeros((rows, cols), dtype=np.float64)
+    for _ in range(n_rect):
+        c0, c1 = np.sort(rng.integers(0, cols, 2))
+        r0, r1 = np.sort(rng.integers(0, rows, 2))
+        img[r0:r1 + 1, c0:c1 + 1] = rng.uniform(0.0, 1.0)
+    gu, gv = rng.uniform(-0.25, 0.25, 2)
+    u = np.linspace(0.0, 1.0, rows)[:, None]
+    v = np.linspace(0.0, 1.0, cols)[None, :]
+    img = img + gu * u + gv * v
+    return np.clip(img, 0.0, 1.0)
+
+
+def gen_noise(rng: np.random.Generator, shape, sigma: float = 1e-3) -> np.ndarray:
+    return rng.normal(0.0, sigma, size=shape)
+
+
+def gen_conv_pair(rng: np.random.Generator, K: int, N: int):
+    """Channel h (length K) and source s (length N), both N(0,1) float64."""
+    h = rng.standard_normal(K)
+    s = rng.standard_normal(N)
+    return h, s
+
+
+def gen_coefficients(rng: np.random.Generator, n: int, density: float = 1.0) -> np.ndarray:
+    """Random coefficient vector (for operator parity); optional sparsity."""
+    x = rng.standard_normal(n)
+    if density < 1.0:
+        x = x * (rng.uniform(0.0, 1.0, n) < density)
+    return x
+
+
+def gen_batched_config(rng: np.random.Generator, n_images: int = 64):
+    """Per-image (rows, cols, levels, taps, sigma, radius) for the uneven batch."""
+    sides = np.arange(512, 4096 + 1, 256)
+    out = []
+    for _ in range(n_images):
+        rows = int(rng.choice(sides))
+        cols = int(rng.choice(sides))
+        levels = int(rng.choice([3, 4, 5]))
+        taps = int(rng.choice([2, 8, 16]))
+        sigma = float(rng.uniform(1.0, 4.0))
+        radius = int(math.ceil(3.0 * sigma))
+        out.append(dict(rows=rows, cols=cols, levels=levels, taps=taps,
+                        sigma=sigma, radius=radius))
+    return out
