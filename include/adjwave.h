@@ -1,0 +1,213 @@
+/*
+ * adjwave.h - C ABI of the MI355X (gfx950) library for the deblurring operator
+ * A = R W, its adjoint A^* = W^* R^*, one FISTA iteration on eq. (1), and the
+ * blind-channel convolution adjoint pair.
+ *
+ * Paper: J. Folberth and S. Becker, "Efficient Adjoint Computation for Wavelet
+ * and Convolution Operators", IEEE Signal Processing Magazine, Lecture Notes,
+ * 2016.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory   Every data pointer is a DEVICE pointer owned by the caller. The
+ *          library never allocates device memory in these calls: buffers for
+ *          intermediates come from the caller as a workspace whose size
+ *          aw_workspace_size() reports. Descriptor structs are host memory,
+ *          read during the call only.
+ * Streams  Work is enqueued on `stream` (a hipStream_t passed as void*; NULL
+ *          means the default stream). No call synchronises the device; the
+ *          caller orders reads of outputs after the stream.
+ * Layout   Images are row-major [batch][rows][cols]. Coefficient vectors are
+ *          [batch][ncoef] with subbands a_J, H_J, V_J, D_J, H_{J-1}, ...,
+ *          D_1, each row-major (K^r_j x K^c_j). H = high-pass along rows and
+ *          low-pass along columns, V = low-pass along rows and high-pass along
+ *          columns, D = high-pass along both.
+ * dtype    AW_F32 or AW_F64, for every floating-point buffer of a call.
+ * Errors   A negative aw_status. Arguments are validated on the host before
+ *          anything is enqueued; on error nothing is launched and
+ *          aw_last_error() returns a message (thread-local). AW_EHIP reports a
+ *          HIP launch error; its message carries the HIP error string.
+ * Threads  Entry points are thread-safe; calls that share a workspace or an
+ *          output buffer must be ordered by the caller.
+ */
+#ifndef ADJWAVE_H
+#define ADJWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AW_OK = 0,
+  AW_EINVAL = -1,        /* invalid argument (NULL, size, filter, radius ...) */
+  AW_EUNSUPPORTED = -2,  /* valid request that this build does not implement */
+  AW_EHIP = -3           /* HIP runtime / launch failure                     */
+} aw_status;
+
+typedef enum { AW_F32 = 0, AW_F64 = 1 } aw_dtype;
+
+/* Boundary handling of the wavelet transform (Sec. "A few signal extensions").
+ *  AW_BC_ZPD     zero boundary: the zero-boundary core alone (no explicit
+ *                extension); K = floor((N + L - 1)/2) per band.
+ *  AW_BC_SYM     half-point symmetric extension by L' = L - 1 on each side,
+ *                fold weights 1/mult (the paper's (E_sym^dagger)^*);
+ *                K = floor((N + 3L - 3)/2).
+ *  AW_BC_PER     critically sampled circular transform (square, orthogonal):
+ *                c[k] = sum_q f[q] y[(2k+q) mod N], K = N/2; every level's
+ *                length must be even.
+ *  AW_BC_PER_EXT periodic extension by L' with fold weights 1/mult (the
+ *                paper's E_per and (E_per^dagger)^*); K as for AW_BC_SYM. */
+typedef enum { AW_BC_ZPD = 0, AW_BC_SYM = 1, AW_BC_PER = 2, AW_BC_PER_EXT = 3 } aw_bc;
+
+#define AW_MAX_TAPS 16
+#define AW_MAX_LEVELS 8
+#define AW_MAX_RADIUS 12
+
+/* Multi-level 2-D orthogonal wavelet transform of a rows x cols image.
+ * lo[0..filter_len) is the reconstruction low-pass filter h (orthonormal even
+ * shifts, sum sqrt(2)); the high-pass is g[k] = (-1)^k h[L-1-k].
+ * filter_len must be 2, 8 or 16 (Haar, Daubechies-4, Daubechies-8);
+ * 1 <= levels <= AW_MAX_LEVELS. */
+typedef struct {
+  int32_t rows, cols;
+  int32_t levels;
+  int32_t filter_len;
+  int32_t bc; /* aw_bc */
+  double lo[AW_MAX_TAPS];
+} aw_wavelet;
+
+/* Separable blur R with half-point reflexive boundaries (Sec. "Example 1"):
+ * (R x)[i] = sum_{u=-r}^{r} g[u] x[refl(i-u)] along rows, then columns;
+ * taps[u + radius] = g[u]; 0 <= radius <= AW_MAX_RADIUS. The taps need not be
+ * symmetric: blur_adjoint applies the structural adjoint in every case. */
+typedef struct {
+  int32_t rows, cols, radius;
+  double taps[2 * AW_MAX_RADIUS + 1];
+} aw_blur;
+
+/* ------------------------------------------------------------ utilities */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* aw_last_error(void);
+
+/* Orthonormal minimum-phase Daubechies scaling filter of length `taps`
+ * (2, 4, ..., 16), by spectral factorisation (host computation; writes taps
+ * doubles to lo_out, sum sqrt(2)). Sec. "The adjoint for orthogonal wavelets"
+ * names Haar and Daubechies wavelets. */
+aw_status aw_daubechies(int32_t taps, double* lo_out);
+
+/* Normalised Gaussian PSF taps g[u] ~ exp(-u^2/(2 sigma^2)), |u| <= radius
+ * (host computation; writes 2*radius+1 doubles). */
+aw_status aw_gaussian_psf(double sigma, int32_t radius, double* taps_out);
+
+/* Coefficient layout: ncoef per image and the per-level sizes along rows and
+ * columns, sub_rows[0] = rows, sub_rows[j] = K^r_j (arrays of levels+1
+ * entries; either may be NULL). */
+aw_status aw_wavelet_layout(const aw_wavelet* w, int64_t* ncoef, int32_t* sub_rows,
+                            int32_t* sub_cols);
+
+/* Workspace bytes that every entry point below needs for this problem and
+ * batch (w or b may be NULL when the call does not use it). */
+aw_status aw_workspace_size(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype,
+                            int32_t batch, size_t* bytes);
+
+/* ------------------------------------------------------ wavelet operators */
+
+/* img = W coef: multi-level synthesis (reconstruction), per level
+ * W = E^dagger Phi^* (Sec. "A few signal extensions"). */
+aw_status wavelet_synth(const aw_wavelet* w, aw_dtype dtype, int32_t batch, const void* coef,
+                        void* img, void* workspace, size_t workspace_bytes, void* stream);
+
+/* coef = W^* img: the true adjoint of wavelet_synth, per level
+ * W^* = W^*_zpd (E^dagger)^* (eq. 2; for orthogonal filters W^*_zpd is the
+ * zero-boundary analysis). */
+aw_status wavelet_synth_adjoint(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                                const void* img, void* coef, void* workspace,
+                                size_t workspace_bytes, void* stream);
+
+/* coef = W^dagger img: wavelet analysis, per level W^dagger = W^dagger_zpd E
+ * (Sec. "A few signal extensions"); the "pseudoinverse approximation" of W^*. */
+aw_status aw_wavelet_analysis(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                              const void* img, void* coef, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* img = (W^dagger)^* coef = per level E^* Phi^* (synthesis with a summing
+ * fold); the adjoint of aw_wavelet_analysis. */
+aw_status aw_wavelet_analysis_adjoint(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                                      const void* coef, void* img, void* workspace,
+                                      size_t workspace_bytes, void* stream);
+
+/* --------------------------------------------------------- blur operators */
+
+/* y = R x (Sec. "Example 1": Gaussian PSF, reflexive boundaries). x != y. */
+aw_status blur(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* x, void* y,
+               void* stream);
+
+/* x = R^* y: correlation with the PSF on the extended domain, halo folded back
+ * by summation onto its reflexive preimages. x != y. */
+aw_status blur_adjoint(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* y,
+                       void* x, void* stream);
+
+/* ---------------------------------------------------- composed operators */
+
+/* img = A coef = R W coef (eq. 1). w and b must describe the same image size. */
+aw_status aw_apply_A(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                     const void* coef, void* img, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
+/* coef = A^* img = W^* R^* img (the gradient map of Sec. "Example 1"). */
+aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype,
+                             int32_t batch, const void* img, void* coef, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ FISTA */
+
+/* State of FISTA (Beck & Teboulle) on eq. (1) for `batch` independent images
+ * sharing one size, filter and PSF.
+ *   x      [batch][ncoef]  x_{k-1} on entry, x_k on return (in place)
+ *   y      [batch][ncoef]  y_k on entry, y_{k+1} on return (in place)
+ *   resid  [batch][rows][cols]  written: A y_k - b
+ *   obj    device doubles [batch][2] or NULL: written when want_objective:
+ *          obj[2i] = 1/2 ||A y_k - b||^2, obj[2i+1] = ||x_k||_1
+ *   k      iteration index (>= 1), incremented by fista_step
+ *   t      t_k (t_1 = 1), replaced by t_{k+1} by fista_step            */
+typedef struct {
+  void* x;
+  void* y;
+  void* resid;
+  double* obj;
+  int64_t k;
+  double t;
+} aw_fista_state;
+
+/* One FISTA iteration with constant step 1/L:
+ *   x_k = soft(y_k - A^*(A y_k - b)/L, lambda/L),
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+ *   y_{k+1} = x_k + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1}).
+ * b is [batch][rows][cols]. L > 0, lambda >= 0. */
+aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                     const void* b_obs, double L, double lambda, aw_fista_state* state,
+                     int32_t want_objective, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
+/* ------------------------------------------------- convolution adjoints */
+
+/* Blind-channel pair (Sec. "Example 2"), `batch` independent (h, s) pairs:
+ *   resid[t]  = (h * s)[t] - x_obs[t],  t < K+N-1  (full linear convolution)
+ *   grad_h[n] = sum_{k<N} s[k] resid[k+n], n < K  (S^* r, cross-correlation)
+ *   grad_s[n] = sum_{k<K} h[k] resid[k+n], n < N  (H^* r)
+ * h: [batch][K], s: [batch][N], x_obs/resid: [batch][K+N-1]. x_obs may be
+ * NULL (treated as zero). grad_h / grad_s may be NULL (not computed).
+ * resid must not alias the inputs. */
+aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N, const void* h,
+                            const void* s, const void* x_obs, void* resid, void* grad_h,
+                            void* grad_s, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADJWAVE_H */

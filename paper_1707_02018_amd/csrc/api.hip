@@ -1,0 +1,574 @@
+// C ABI (include/adjwave.h): validation, coefficient layout, workspace
+// carving, and the per-level launch sequences of W, W^*, W^dagger,
+// (W^dagger)^*, R, R^*, A, A^*, one FISTA iteration and the convolution pair.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/adjwave.h"
+#include "aw_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+aw_status fail(aw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+aw_status ok() {
+  g_err.clear();
+  return AW_OK;
+}
+
+aw_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(AW_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return AW_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------ wavelet plan
+struct WavePlan {
+  int J = 0, L = 0, bc = 0, e = 0;
+  int rows = 0, cols = 0;
+  int sr[AW_MAX_LEVELS + 1] = {0}, sc[AW_MAX_LEVELS + 1] = {0};
+  long long ncoef = 0;
+  long long off_hvd[AW_MAX_LEVELS + 1] = {0};  // offset of H_j in the coefficient vector
+  double lo[AW_MAX_TAPS] = {0};
+};
+
+int coef_len(int N, int L, int bc, int e) {
+  if (bc == aw::PER) return N / 2;
+  return (N + 2 * e + L - 1) / 2;
+}
+
+aw_status make_plan(const aw_wavelet* w, WavePlan& p) {
+  if (!w) return fail(AW_EINVAL, "wavelet descriptor is NULL");
+  if (w->rows < 1 || w->cols < 1) return fail(AW_EINVAL, "image size %dx%d", w->rows, w->cols);
+  if (w->levels < 1 || w->levels > AW_MAX_LEVELS)
+    return fail(AW_EINVAL, "levels=%d outside [1, %d]", w->levels, AW_MAX_LEVELS);
+  if (w->filter_len != 2 && w->filter_len != 8 && w->filter_len != 16)
+    return fail(AW_EINVAL, "filter_len=%d (supported: 2, 8, 16)", w->filter_len);
+  if (w->bc < AW_BC_ZPD || w->bc > AW_BC_PER_EXT) return fail(AW_EINVAL, "bc=%d", w->bc);
+  p.J = w->levels;
+  p.L = w->filter_len;
+  p.bc = w->bc;
+  p.e = (p.bc == aw::SYM || p.bc == aw::PER_EXT) ? p.L - 1 : 0;
+  p.rows = w->rows;
+  p.cols = w->cols;
+  for (int k = 0; k < p.L; ++k) {
+    if (!std::isfinite(w->lo[k])) return fail(AW_EINVAL, "filter tap %d is not finite", k);
+    p.lo[k] = w->lo[k];
+  }
+  for (int m = 0; m < p.L / 2; ++m) {  // orthonormal even shifts
+    double s = 0.0;
+    for (int k = 0; k + 2 * m < p.L; ++k) s += p.lo[k] * p.lo[k + 2 * m];
+    if (std::fabs(s - (m == 0 ? 1.0 : 0.0)) > 1e-12)
+      return fail(AW_EINVAL, "filter is not orthonormal (shift %d: %.3e)", 2 * m, s);
+  }
+  p.sr[0] = p.rows;
+  p.sc[0] = p.cols;
+  for (int j = 1; j <= p.J; ++j) {
+    if (p.bc == aw::PER && (p.sr[j - 1] % 2 || p.sc[j - 1] % 2))
+      return fail(AW_EINVAL, "periodic mode needs even sizes at every level (level %d: %dx%d)", j,
+                  p.sr[j - 1], p.sc[j - 1]);
+    p.sr[j] = coef_len(p.sr[j - 1], p.L, p.bc, p.e);
+    p.sc[j] = coef_len(p.sc[j - 1], p.L, p.bc, p.e);
+  }
+  const long long lim = (1LL << 31) - 1;
+  for (int j = 0; j <= p.J; ++j) {
+    const long long ext = (long long)(p.sr[j] + 2 * p.e) * (p.sc[j] + 2 * p.e);
+    if (ext > lim) return fail(AW_EINVAL, "level %d plane too large", j);
+  }
+  long long n = (long long)p.sr[p.J] * p.sc[p.J];
+  p.off_hvd[p.J] = n;
+  for (int j = p.J; j >= 1; --j) {
+    n += 3LL * p.sr[j] * p.sc[j];
+    if (j > 1) p.off_hvd[j - 1] = n;
+  }
+  p.ncoef = n;
+  return AW_OK;
+}
+
+aw_status make_blur(const aw_blur* b, aw::BlurDesc& d) {
+  if (!b) return fail(AW_EINVAL, "blur descriptor is NULL");
+  if (b->rows < 1 || b->cols < 1) return fail(AW_EINVAL, "image size %dx%d", b->rows, b->cols);
+  if ((long long)b->rows * b->cols > (1LL << 31) - 1) return fail(AW_EINVAL, "image too large");
+  if (b->radius < 0 || b->radius > AW_MAX_RADIUS)
+    return fail(AW_EINVAL, "radius=%d outside [0, %d]", b->radius, AW_MAX_RADIUS);
+  d.rows = b->rows;
+  d.cols = b->cols;
+  d.radius = b->radius;
+  for (int i = 0; i < 2 * b->radius + 1; ++i) {
+    if (!std::isfinite(b->taps[i])) return fail(AW_EINVAL, "PSF tap %d is not finite", i);
+    d.taps[i] = b->taps[i];
+  }
+  return AW_OK;
+}
+
+size_t dsize(aw_dtype t) { return t == AW_F64 ? 8 : 4; }
+
+aw_status check_dtype(aw_dtype t) {
+  if (t != AW_F32 && t != AW_F64) return fail(AW_EINVAL, "dtype=%d", (int)t);
+  return AW_OK;
+}
+
+// ------------------------------------------------------------ workspace
+// [a_1 .. a_{J-1}] [extended plane] [image] [gradient] [partials_r] [partials_l1]
+struct WsLayout {
+  size_t a_off[AW_MAX_LEVELS + 1] = {0};
+  size_t ext_off = 0, img_off = 0, grad_off = 0, pr_off = 0, pl_off = 0;
+  size_t wave_end = 0;  // bytes used by the wavelet operators alone
+  size_t total = 0;
+  int n_pr = 0, n_pl = 0;
+};
+
+WsLayout layout_ws(const WavePlan* p, const aw::BlurDesc* b, aw_dtype dt, int batch) {
+  WsLayout l;
+  const size_t ts = dsize(dt);
+  size_t off = 0;
+  if (p) {
+    for (int j = 1; j < p->J; ++j) {
+      l.a_off[j] = off;
+      off = align_up(off + (size_t)p->sr[j] * p->sc[j] * batch * ts);
+    }
+    l.ext_off = off;
+    if (p->bc == aw::PER_EXT) {
+      size_t mx = 0;
+      for (int j = 1; j <= p->J; ++j) {
+        const size_t m = (size_t)(p->sr[j - 1] + 2 * p->e) * (p->sc[j - 1] + 2 * p->e);
+        if (m > mx) mx = m;
+      }
+      off = align_up(off + mx * batch * ts);
+    }
+  }
+  l.wave_end = off;
+  const int rows = p ? p->rows : (b ? b->rows : 0);
+  const int cols = p ? p->cols : (b ? b->cols : 0);
+  l.img_off = off;
+  off = align_up(off + (size_t)rows * cols * batch * ts);
+  l.grad_off = off;
+  if (p) off = align_up(off + (size_t)p->ncoef * batch * ts);
+  l.n_pr = b ? aw::blur_tiles(dt == AW_F64, *b) : 0;
+  l.n_pl = p ? aw::fista_prox_blocks(p->ncoef) : 0;
+  l.pr_off = off;
+  off = align_up(off + (size_t)l.n_pr * batch * sizeof(double));
+  l.pl_off = off;
+  off = align_up(off + (size_t)l.n_pl * batch * sizeof(double));
+  l.total = off;
+  return l;
+}
+
+char* wsp(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+aw_status need_ws(void* ws, size_t have, size_t need) {
+  if (need > 0 && !ws) return fail(AW_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+  if (have < need) return fail(AW_EINVAL, "workspace too small: %zu < %zu bytes", have, need);
+  return AW_OK;
+}
+
+// ---------------------------------------------------------- level sequences
+aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* coef, void* img,
+                        void* ws, const WsLayout& l, int pinv, hipStream_t s) {
+  const size_t ts = dsize(dt);
+  const int dtype = dt == AW_F64;
+  for (int j = p.J; j >= 1; --j) {
+    aw::SynthLevel d{};
+    d.a = (j == p.J) ? coef : wsp(ws, l.a_off[j]);
+    d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
+    d.hvd = static_cast<const char*>(coef) + p.off_hvd[j] * ts;
+    d.stride_hvd = p.ncoef;
+    d.out = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
+    d.stride_out = (long long)p.sr[j - 1] * p.sc[j - 1];
+    d.r = {p.sr[j - 1], p.sr[j], p.e};
+    d.c = {p.sc[j - 1], p.sc[j], p.e};
+    d.bc = p.bc;
+    d.pinv = pinv;
+    hipError_t e;
+    if (p.bc == aw::PER_EXT) {
+      // extended synthesis (zero-boundary core on length N + 2e), then fold
+      aw::SynthLevel z = d;
+      z.bc = aw::ZPD;
+      z.r = {p.sr[j - 1] + 2 * p.e, p.sr[j], 0};
+      z.c = {p.sc[j - 1] + 2 * p.e, p.sc[j], 0};
+      z.out = wsp(ws, l.ext_off);
+      z.stride_out = (long long)z.r.N * z.c.N;
+      if (aw::synth_level_lds(dtype, p.L, z) > 160 * 1024)
+        return fail(AW_EUNSUPPORTED, "tile window exceeds LDS at level %d", j);
+      e = aw::launch_synth_level(dtype, p.L, p.lo, z, batch, s);
+      if (e != hipSuccess) return hip_check(e, "synthesis launch");
+      aw::FoldLevel f{};
+      f.ext = z.out;
+      f.out = d.out;
+      f.stride_ext = z.stride_out;
+      f.stride_out = d.stride_out;
+      f.r = d.r;
+      f.c = d.c;
+      f.bc = p.bc;
+      f.pinv = pinv;
+      e = aw::launch_fold_level(dtype, f, batch, s);
+      if (e != hipSuccess) return hip_check(e, "fold launch");
+    } else {
+      if (aw::synth_level_lds(dtype, p.L, d) > 160 * 1024)
+        return fail(AW_EUNSUPPORTED, "tile window exceeds LDS at level %d", j);
+      e = aw::launch_synth_level(dtype, p.L, p.lo, d, batch, s);
+      if (e != hipSuccess) return hip_check(e, "synthesis launch");
+    }
+  }
+  return AW_OK;
+}
+
+aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* img, void* coef,
+                       void* ws, const WsLayout& l, int pinv, hipStream_t s) {
+  const size_t ts = dsize(dt);
+  for (int j = 1; j <= p.J; ++j) {
+    aw::AnaLevel d{};
+    d.in = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
+    d.stride_in = (long long)p.sr[j - 1] * p.sc[j - 1];
+    d.a = (j == p.J) ? coef : wsp(ws, l.a_off[j]);
+    d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
+    d.hvd = static_cast<char*>(coef) + p.off_hvd[j] * ts;
+    d.stride_hvd = p.ncoef;
+    d.r = {p.sr[j - 1], p.sr[j], p.e};
+    d.c = {p.sc[j - 1], p.sc[j], p.e};
+    d.bc = p.bc;
+    d.pinv = pinv;
+    hipError_t e = aw::launch_ana_level(dt == AW_F64, p.L, p.lo, d, batch, s);
+    if (e != hipSuccess) return hip_check(e, "analysis launch");
+  }
+  return AW_OK;
+}
+
+aw_status wave_common(const aw_wavelet* w, aw_dtype dt, int batch, const void* in, void* out,
+                      void* ws, size_t wsb, WavePlan& p, WsLayout& l) {
+  aw_status st;
+  if ((st = check_dtype(dt)) != AW_OK) return st;
+  if ((st = make_plan(w, p)) != AW_OK) return st;
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  if (!in || !out) return fail(AW_EINVAL, "NULL data pointer");
+  l = layout_ws(&p, nullptr, dt, batch);
+  return need_ws(ws, wsb, l.wave_end);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aw_last_error(void) { return g_err.c_str(); }
+
+aw_status aw_daubechies(int32_t taps, double* lo_out) {
+  if (!lo_out) return fail(AW_EINVAL, "output pointer is NULL");
+  if (taps < 2 || taps > AW_MAX_TAPS || taps % 2) return fail(AW_EINVAL, "taps=%d", taps);
+  typedef std::complex<double> cd;
+  const int p = taps / 2;
+  std::vector<cd> zeros(p, cd(-1.0, 0.0));
+  if (p > 1) {
+    // roots of P(y) = sum_{k<p} C(p-1+k, k) y^k by Durand-Kerner iteration
+    const int deg = p - 1;
+    std::vector<double> c(p);
+    for (int k = 0; k < p; ++k) {
+      double b = 1.0;
+      for (int i = 1; i <= k; ++i) b = b * (p - 1 + i) / i;
+      c[k] = b;
+    }
+    auto P = [&](cd y) {
+      cd v = 0.0;
+      for (int k = deg; k >= 0; --k) v = v * y + c[k];
+      return v;
+    };
+    auto dP = [&](cd y) {
+      cd v = 0.0;
+      for (int k = deg; k >= 1; --k) v = v * y + c[k] * (double)k;
+      return v;
+    };
+    std::vector<cd> r(deg);
+    for (int i = 0; i < deg; ++i) r[i] = std::pow(cd(0.4, 0.9), i);
+    for (int it = 0; it < 2000; ++it) {
+      double moved = 0.0;
+      for (int i = 0; i < deg; ++i) {
+        cd den = c[deg];
+        for (int j = 0; j < deg; ++j)
+          if (j != i) den *= (r[i] - r[j]);
+        const cd step = P(r[i]) / den;
+        r[i] -= step;
+        moved = std::max(moved, std::abs(step));
+      }
+      if (moved < 1e-16) break;
+    }
+    for (int i = 0; i < deg; ++i)  // Newton polish on the original polynomial
+      for (int it = 0; it < 3; ++it) {
+        const cd d = dP(r[i]);
+        if (std::abs(d) > 0) r[i] -= P(r[i]) / d;
+      }
+    for (int i = 0; i < deg; ++i) {
+      const cd b = 2.0 - 4.0 * r[i];
+      const cd disc = std::sqrt(b * b - 4.0);
+      const cd z1 = (b + disc) / 2.0, z2 = (b - disc) / 2.0;
+      zeros.push_back(std::abs(z1) < 1.0 ? z1 : z2);
+    }
+  }
+  std::vector<cd> poly(1, cd(1.0, 0.0));  // descending powers
+  for (const cd& z : zeros) {
+    std::vector<cd> nx(poly.size() + 1, cd(0.0, 0.0));
+    for (size_t i = 0; i < poly.size(); ++i) {
+      nx[i] += poly[i];
+      nx[i + 1] -= poly[i] * z;
+    }
+    poly.swap(nx);
+  }
+  double sum = 0.0;
+  for (int k = 0; k < taps; ++k) sum += poly[k].real();
+  for (int k = 0; k < taps; ++k) lo_out[k] = poly[k].real() * std::sqrt(2.0) / sum;
+  return ok();
+}
+
+aw_status aw_gaussian_psf(double sigma, int32_t radius, double* taps_out) {
+  if (!taps_out) return fail(AW_EINVAL, "output pointer is NULL");
+  if (!(sigma > 0.0) || radius < 0 || radius > AW_MAX_RADIUS)
+    return fail(AW_EINVAL, "sigma=%g radius=%d", sigma, radius);
+  double s = 0.0;
+  for (int u = -radius; u <= radius; ++u) {
+    taps_out[u + radius] = std::exp(-(double)u * u / (2.0 * sigma * sigma));
+    s += taps_out[u + radius];
+  }
+  for (int i = 0; i < 2 * radius + 1; ++i) taps_out[i] /= s;
+  return ok();
+}
+
+aw_status aw_wavelet_layout(const aw_wavelet* w, int64_t* ncoef, int32_t* sub_rows,
+                            int32_t* sub_cols) {
+  WavePlan p;
+  aw_status st = make_plan(w, p);
+  if (st != AW_OK) return st;
+  if (ncoef) *ncoef = p.ncoef;
+  for (int j = 0; j <= p.J; ++j) {
+    if (sub_rows) sub_rows[j] = p.sr[j];
+    if (sub_cols) sub_cols[j] = p.sc[j];
+  }
+  return ok();
+}
+
+aw_status aw_workspace_size(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                            size_t* bytes) {
+  aw_status st;
+  if (!bytes) return fail(AW_EINVAL, "bytes is NULL");
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  WavePlan p;
+  aw::BlurDesc bd;
+  if (w && (st = make_plan(w, p)) != AW_OK) return st;
+  if (b && (st = make_blur(b, bd)) != AW_OK) return st;
+  *bytes = layout_ws(w ? &p : nullptr, b ? &bd : nullptr, dtype, batch).total;
+  return ok();
+}
+
+aw_status wavelet_synth(const aw_wavelet* w, aw_dtype dtype, int32_t batch, const void* coef,
+                        void* img, void* workspace, size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  WsLayout l;
+  aw_status st = wave_common(w, dtype, batch, coef, img, workspace, workspace_bytes, p, l);
+  if (st != AW_OK) return st;
+  st = run_synthesis(p, dtype, batch, coef, img, workspace, l, 1, (hipStream_t)stream);
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_wavelet_analysis_adjoint(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                                      const void* coef, void* img, void* workspace,
+                                      size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  WsLayout l;
+  aw_status st = wave_common(w, dtype, batch, coef, img, workspace, workspace_bytes, p, l);
+  if (st != AW_OK) return st;
+  st = run_synthesis(p, dtype, batch, coef, img, workspace, l, 0, (hipStream_t)stream);
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status wavelet_synth_adjoint(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                                const void* img, void* coef, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  WsLayout l;
+  aw_status st = wave_common(w, dtype, batch, img, coef, workspace, workspace_bytes, p, l);
+  if (st != AW_OK) return st;
+  st = run_analysis(p, dtype, batch, img, coef, workspace, l, 1, (hipStream_t)stream);
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_wavelet_analysis(const aw_wavelet* w, aw_dtype dtype, int32_t batch,
+                              const void* img, void* coef, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  WsLayout l;
+  aw_status st = wave_common(w, dtype, batch, img, coef, workspace, workspace_bytes, p, l);
+  if (st != AW_OK) return st;
+  st = run_analysis(p, dtype, batch, img, coef, workspace, l, 0, (hipStream_t)stream);
+  return st == AW_OK ? ok() : st;
+}
+
+static aw_status blur_common(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* in,
+                             void* out, aw::BlurDesc& d) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if ((st = make_blur(b, d)) != AW_OK) return st;
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  if (!in || !out) return fail(AW_EINVAL, "NULL data pointer");
+  if (in == out) return fail(AW_EINVAL, "blur input and output must not alias");
+  return AW_OK;
+}
+
+aw_status blur(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* x, void* y,
+               void* stream) {
+  aw::BlurDesc d;
+  aw_status st = blur_common(b, dtype, batch, x, y, d);
+  if (st != AW_OK) return st;
+  st = hip_check(aw::launch_blur(dtype == AW_F64, d, batch, x, y, nullptr, nullptr,
+                                 (hipStream_t)stream),
+                 "blur launch");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status blur_adjoint(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* y, void* x,
+                       void* stream) {
+  aw::BlurDesc d;
+  aw_status st = blur_common(b, dtype, batch, y, x, d);
+  if (st != AW_OK) return st;
+  st = hip_check(aw::launch_blur_adjoint(dtype == AW_F64, d, batch, y, x, (hipStream_t)stream),
+                 "blur_adjoint launch");
+  return st == AW_OK ? ok() : st;
+}
+
+static aw_status op_common(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                           const void* in, void* out, void* ws, size_t wsb, WavePlan& p,
+                           aw::BlurDesc& d, WsLayout& l) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if ((st = make_plan(w, p)) != AW_OK) return st;
+  if ((st = make_blur(b, d)) != AW_OK) return st;
+  if (d.rows != p.rows || d.cols != p.cols)
+    return fail(AW_EINVAL, "wavelet %dx%d and blur %dx%d sizes differ", p.rows, p.cols, d.rows,
+                d.cols);
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  if (!in || !out) return fail(AW_EINVAL, "NULL data pointer");
+  l = layout_ws(&p, &d, dtype, batch);
+  return need_ws(ws, wsb, l.total);
+}
+
+aw_status aw_apply_A(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                     const void* coef, void* img, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = op_common(w, b, dtype, batch, coef, img, workspace, workspace_bytes, p, d, l);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  void* tmp = wsp(workspace, l.img_off);
+  if ((st = run_synthesis(p, dtype, batch, coef, tmp, workspace, l, 1, s)) != AW_OK) return st;
+  st = hip_check(aw::launch_blur(dtype == AW_F64, d, batch, tmp, img, nullptr, nullptr, s),
+                 "blur launch");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                             const void* img, void* coef, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = op_common(w, b, dtype, batch, img, coef, workspace, workspace_bytes, p, d, l);
+  if (st != AW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  void* tmp = wsp(workspace, l.img_off);
+  st = hip_check(aw::launch_blur_adjoint(dtype == AW_F64, d, batch, img, tmp, s),
+                 "blur_adjoint launch");
+  if (st != AW_OK) return st;
+  st = run_analysis(p, dtype, batch, tmp, coef, workspace, l, 1, s);
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                     const void* b_obs, double L, double lambda, aw_fista_state* state,
+                     int32_t want_objective, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  if (!state) return fail(AW_EINVAL, "state is NULL");
+  aw_status st = op_common(w, b, dtype, batch, b_obs, state->resid, workspace, workspace_bytes, p,
+                           d, l);
+  if (st != AW_OK) return st;
+  if (!state->x || !state->y) return fail(AW_EINVAL, "state x / y is NULL");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(AW_EINVAL, "L=%g", L);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
+  if (state->k < 1) return fail(AW_EINVAL, "k=%lld (iterations count from 1)", (long long)state->k);
+  if (!(state->t >= 1.0)) return fail(AW_EINVAL, "t=%g (t_1 = 1, increasing)", state->t);
+  const bool obj = want_objective && state->obj;
+  hipStream_t s = (hipStream_t)stream;
+  const int dtype_i = dtype == AW_F64;
+  void* img = wsp(workspace, l.img_off);
+  void* grad = wsp(workspace, l.grad_off);
+  double* pr = reinterpret_cast<double*>(wsp(workspace, l.pr_off));
+  double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
+  // r = R W y - b
+  if ((st = run_synthesis(p, dtype, batch, state->y, img, workspace, l, 1, s)) != AW_OK) return st;
+  if ((st = hip_check(aw::launch_blur(dtype_i, d, batch, img, state->resid, b_obs,
+                                      obj ? pr : nullptr, s),
+                      "blur launch")) != AW_OK)
+    return st;
+  // g = W^* R^* r
+  if ((st = hip_check(aw::launch_blur_adjoint(dtype_i, d, batch, state->resid, img, s),
+                      "blur_adjoint launch")) != AW_OK)
+    return st;
+  if ((st = run_analysis(p, dtype, batch, img, grad, workspace, l, 1, s)) != AW_OK) return st;
+  // prox + momentum
+  const double t = state->t;
+  const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+  const double beta = (t - 1.0) / tn;
+  if ((st = hip_check(aw::launch_fista_prox(dtype_i, batch, p.ncoef, grad, state->x, state->y,
+                                            1.0 / L, lambda / L, beta, obj ? pl : nullptr, s),
+                      "prox launch")) != AW_OK)
+    return st;
+  if (obj) {
+    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, state->obj, 2, 0, s),
+                        "reduce launch")) != AW_OK)
+      return st;
+    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pl, pl, 1.0, state->obj, 2, 1, s),
+                        "reduce launch")) != AW_OK)
+      return st;
+  }
+  state->t = tn;
+  state->k += 1;
+  return ok();
+}
+
+aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N, const void* h,
+                            const void* s, const void* x_obs, void* resid, void* grad_h,
+                            void* grad_s, void* stream) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (batch < 1 || K < 1 || N < 1) return fail(AW_EINVAL, "batch=%d K=%d N=%d", batch, K, N);
+  if ((long long)K + N - 1 > (1LL << 31) - 1) return fail(AW_EINVAL, "K+N-1 too large");
+  if (!h || !s || !resid) return fail(AW_EINVAL, "NULL data pointer");
+  if (resid == h || resid == s || resid == x_obs)
+    return fail(AW_EINVAL, "resid must not alias the inputs");
+  st = hip_check(aw::launch_conv_pair(dtype == AW_F64, batch, K, N, h, s, x_obs, resid, grad_h,
+                                      grad_s, (hipStream_t)stream),
+                 "conv launch");
+  return st == AW_OK ? ok() : st;
+}
+
+}  // extern "C"

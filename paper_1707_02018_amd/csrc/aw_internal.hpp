@@ -1,0 +1,179 @@
+// Internal declarations shared by the kernel files and the C-ABI layer.
+//
+// Index conventions (Folberth & Becker, Sec. "A few signal extensions"):
+//  * A level maps a length-N signal to K coefficients per band. The zero-
+//    boundary core reads the extended signal u(n), n in [0, M), M = N + 2e,
+//    where u(n) copies y[src(n - e)].
+//  * Synthesis core: s(n) = sum_{m < L/2} c_lo[k0(n) - m] h[2m + par(n)]
+//                          + c_hi[k0(n) - m] g[2m + par(n)],
+//    k0(n) = (n + L - 2) / 2 (zero / extended modes) or n / 2 (circular),
+//    par(n) = n mod 2; coefficients outside [0, K) are zero (circular: mod K).
+//  * Analysis core: c_f[k] = sum_{j < L} f[j] u(2k + j - L + 2)  (extended)
+//                   c_f[k] = sum_{j < L} f[j] y[(2k + j) mod N]   (circular).
+//  * Fold: y[p] = w(p) sum_{i : src(i) = p} s(i + e), w = 1/mult (E^dagger)
+//    or 1 (E^*).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aw {
+
+enum Bc { ZPD = 0, SYM = 1, PER = 2, PER_EXT = 3 };
+
+constexpr int kMaxTaps = 16;
+constexpr int kMaxRadius = 12;
+
+__host__ __device__ inline int floordiv(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__host__ __device__ inline int posmod(int a, int b) {
+  int r = a % b;
+  return r < 0 ? r + b : r;
+}
+
+// ---------------------------------------------------------------------------
+// Extension index maps.
+
+// Source sample of extended position i in [-e, N+e).
+__host__ __device__ inline int src_index(int i, int N, int bc) {
+  if (bc == SYM) {
+    int j = posmod(i, 2 * N);
+    return j < N ? j : 2 * N - 1 - j;
+  }
+  if (bc == PER_EXT) return posmod(i, N);
+  return i;
+}
+
+// Calls f(n) for every extended position n = i + e, i in [-e, N+e), whose
+// source is p (half-point symmetric: i = p or 2N-1-p modulo 2N; periodic:
+// i = p modulo N). Returns the number of preimages (the multiplicity).
+template <typename F>
+__host__ __device__ inline int for_each_preimage(int p, int N, int e, int bc, F&& f) {
+  if (e == 0 || bc == ZPD || bc == PER || (p >= e && p < N - e)) {
+    f(p + e);
+    return 1;
+  }
+  int cnt = 0;
+  if (bc == SYM) {
+    const int P = 2 * N;
+    for (int fam = 0; fam < 2; ++fam) {
+      const int base = fam ? (P - 1 - p) : p;
+      for (int i = base - P * ((base + e) / P); i < N + e; i += P) {
+        f(i + e);
+        ++cnt;
+      }
+    }
+  } else {  // PER_EXT
+    for (int i = p - N * ((p + e) / N); i < N + e; i += N) {
+      f(i + e);
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+__host__ __device__ inline int multiplicity(int p, int N, int e, int bc) {
+  return for_each_preimage(p, N, e, bc, [](int) {});
+}
+
+// ---------------------------------------------------------------------------
+// Tile windows (host and device agree on these).
+
+// Extended-position window [nlo, nhi) holding every preimage of outputs
+// [p0, p1) of a half-point symmetric (or zero / circular) fold. Preimages
+// other than p + e lie in [0, e) only if p < e, and in [N+e, N+2e) only if
+// p >= N - e.
+__host__ __device__ inline void fold_window(int p0, int p1, int N, int e, int& nlo, int& nhi) {
+  nlo = (p0 < e) ? 0 : p0 + e;
+  nhi = (p1 > N - e) ? N + 2 * e : p1 + e;
+}
+
+__host__ __device__ inline int synth_k0(int n, int L, int bc) {
+  return bc == PER ? (n >> 1) : ((n + L - 2) >> 1);
+}
+
+// ---------------------------------------------------------------------------
+// Descriptors passed to the kernels.
+
+struct Axis {
+  int N;  // signal length at this level (synthesis output / analysis input)
+  int K;  // coefficients per band
+  int e;  // extension width
+};
+
+template <typename T>
+struct Taps {
+  T h[kMaxTaps];
+  T g[kMaxTaps];
+};
+
+// One synthesis level: (a, H, V, D) -> out (rows.N x cols.N).
+struct SynthLevel {
+  const void* a;
+  const void* hvd;  // H; V = H + Kr*Kc; D = V + Kr*Kc
+  long long stride_a, stride_hvd, stride_out;  // per-image strides (elements)
+  void* out;
+  Axis r, c;
+  int bc;
+  int pinv;  // fold weights 1/mult (1) or 1 (0)
+};
+
+// One analysis level: in (rows.N x cols.N) -> (a, H, V, D).
+struct AnaLevel {
+  const void* in;
+  void* a;
+  void* hvd;
+  long long stride_in, stride_a, stride_hvd;
+  Axis r, c;
+  int bc;
+  int pinv;  // extension weights 1/mult (W^*) or 1 (W^dagger)
+};
+
+// Fold of a materialised extended image (rows.N+2e x cols.N+2e) -> out.
+struct FoldLevel {
+  const void* ext;
+  void* out;
+  long long stride_ext, stride_out;
+  Axis r, c;
+  int bc;
+  int pinv;
+};
+
+struct BlurDesc {
+  int rows, cols, radius;
+  double taps[2 * kMaxRadius + 1];
+};
+
+// Launchers (return hipSuccess or the launch error). dtype: 0 = float, 1 = double.
+hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLevel& d, int batch,
+                              hipStream_t s);
+hipError_t launch_ana_level(int dtype, int L, const double* lo, const AnaLevel& d, int batch,
+                            hipStream_t s);
+hipError_t launch_fold_level(int dtype, const FoldLevel& d, int batch, hipStream_t s);
+size_t synth_level_lds(int dtype, int L, const SynthLevel& d);
+
+// Blur: y = R x; optionally y -= sub (same layout) and per-tile partial sums
+// of 1/2 y^2 (double) into partials[image][tile]. Returns tiles per image.
+hipError_t launch_blur(int dtype, const BlurDesc& b, int batch, const void* x, void* y,
+                       const void* sub, double* partials, hipStream_t s);
+hipError_t launch_blur_adjoint(int dtype, const BlurDesc& b, int batch, const void* y, void* x,
+                               hipStream_t s);
+int blur_tiles(int dtype, const BlurDesc& b);
+
+// FISTA proximal/momentum update over n coefficients per image (in place on
+// x, y), optional per-block l1 partials [image][block]. Returns blocks/image.
+hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad, void* x, void* y,
+                             double inv_L, double thresh, double beta, double* partials,
+                             hipStream_t s);
+int fista_prox_blocks(long long n);
+// out[i*out_stride + out_off] = scale * sum_j partials[i][j] (fixed order).
+hipError_t launch_reduce_partials(int batch, int nparts, const double* partials, double scale,
+                                  double* out, int out_stride, int out_off, hipStream_t s);
+
+hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, const void* s,
+                            const void* x_obs, void* resid, void* grad_h, void* grad_s,
+                            hipStream_t st);
+
+}  // namespace aw

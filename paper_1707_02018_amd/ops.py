@@ -1,0 +1,304 @@
+"""Torch-facing wrappers over the C ABI (argument marshalling only).
+
+Every compute step runs in libadjwave.so on the device. Torch supplies device
+memory (inputs, outputs, workspace) and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+BC_NAMES = tuple(_lib.BC)
+
+
+def daubechies(taps: int) -> np.ndarray:
+    """Orthonormal Daubechies scaling filter of length ``taps`` (2, 4, ..., 16)."""
+    out = (ctypes.c_double * taps)()
+    check("aw_daubechies", load().aw_daubechies(taps, out))
+    return np.array(out[:], dtype=np.float64)
+
+
+def gaussian_psf(sigma: float, radius: int) -> np.ndarray:
+    out = (ctypes.c_double * (2 * radius + 1))()
+    check("aw_gaussian_psf", load().aw_gaussian_psf(float(sigma), int(radius), out))
+    return np.array(out[:], dtype=np.float64)
+
+
+@dataclass
+class WaveletSpec:
+    """Multi-level 2-D orthogonal wavelet transform of a rows x cols image."""
+    rows: int
+    cols: int
+    levels: int
+    taps: int = 8
+    bc: str = "sym"
+    lo: np.ndarray | None = None
+    _c: _lib.Wavelet = field(init=False, repr=False)
+
+    def __post_init__(self):
+        if self.bc not in _lib.BC:
+            raise ValueError(f"bc must be one of {BC_NAMES}")
+        if self.lo is None:
+            self.lo = daubechies(self.taps)
+        self.lo = np.asarray(self.lo, dtype=np.float64)
+        self.taps = len(self.lo)
+        c = _lib.Wavelet()
+        c.rows, c.cols, c.levels, c.filter_len = self.rows, self.cols, self.levels, self.taps
+        c.bc = _lib.BC[self.bc]
+        for k, v in enumerate(self.lo):
+            c.lo[k] = float(v)
+        self._c = c
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+    def layout(self):
+        """(ncoef, row sizes [N, K_1..K_J], col sizes)."""
+        n = ctypes.c_int64()
+        sr = (ctypes.c_int32 * (self.levels + 1))()
+        sc = (ctypes.c_int32 * (self.levels + 1))()
+        check("aw_wavelet_layout", load().aw_wavelet_layout(self.c, ctypes.byref(n), sr, sc))
+        return int(n.value), list(sr), list(sc)
+
+    @property
+    def ncoef(self) -> int:
+        return self.layout()[0]
+
+
+@dataclass
+class BlurSpec:
+    """Separable PSF with reflexive boundaries: Gaussian (sigma, radius) or
+    explicit taps (length 2*radius+1)."""
+    rows: int
+    cols: int
+    sigma: float | None = None
+    radius: int | None = None
+    taps: np.ndarray | None = None
+    _c: _lib.Blur = field(init=False, repr=False)
+
+    def __post_init__(self):
+        if self.taps is None:
+            if self.sigma is None or self.radius is None:
+                raise ValueError("give sigma and radius, or taps")
+            self.taps = gaussian_psf(self.sigma, self.radius)
+        self.taps = np.asarray(self.taps, dtype=np.float64)
+        self.radius = (len(self.taps) - 1) // 2
+        c = _lib.Blur()
+        c.rows, c.cols, c.radius = self.rows, self.cols, self.radius
+        for k, v in enumerate(self.taps):
+            c.taps[k] = float(v)
+        self._c = c
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+# ----------------------------------------------------------------- helpers
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return _lib.F32
+    if t.dtype == torch.float64:
+        return _lib.F64
+    raise TypeError(f"float32 or float64 tensors expected, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("device tensors expected (the library runs on the GPU only)")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensors expected")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def workspace_bytes(w: WaveletSpec | None, b: BlurSpec | None, dtype: torch.dtype,
+                    batch: int) -> int:
+    n = ctypes.c_size_t()
+    code = _lib.F64 if dtype == torch.float64 else _lib.F32
+    check("aw_workspace_size", load().aw_workspace_size(
+        w.c if w is not None else None, b.c if b is not None else None, code, batch,
+        ctypes.byref(n)))
+    return int(n.value)
+
+
+def _workspace(w, b, ref: torch.Tensor, batch: int):
+    n = workspace_bytes(w, b, ref.dtype, batch)
+    return torch.empty(max(n, 1), dtype=torch.uint8, device=ref.device), n
+
+
+def _batch_img(x: torch.Tensor, rows: int, cols: int) -> int:
+    if x.shape[-2:] != (rows, cols):
+        raise ValueError(f"image shape {tuple(x.shape)} does not end in ({rows}, {cols})")
+    return int(np.prod(x.shape[:-2])) if x.dim() > 2 else 1
+
+
+def _batch_coef(x: torch.Tensor, ncoef: int) -> int:
+    if x.shape[-1] != ncoef:
+        raise ValueError(f"coefficient shape {tuple(x.shape)} does not end in {ncoef}")
+    return int(np.prod(x.shape[:-1])) if x.dim() > 1 else 1
+
+
+# ----------------------------------------------------------- wavelet ops
+def _coef_to_img(fn, w: WaveletSpec, coef: torch.Tensor, out=None):
+    _dev(coef)
+    batch = _batch_coef(coef, w.ncoef)
+    if out is None:
+        out = torch.empty(coef.shape[:-1] + (w.rows, w.cols), dtype=coef.dtype, device=coef.device)
+    ws, n = _workspace(w, None, coef, batch)
+    check(fn, getattr(load(), fn)(w.c, _dtype_code(coef), batch, _ptr(coef), _ptr(_dev(out)),
+                                   _ptr(ws), n, _stream(coef)))
+    return out
+
+
+def _img_to_coef(fn, w: WaveletSpec, img: torch.Tensor, out=None):
+    _dev(img)
+    batch = _batch_img(img, w.rows, w.cols)
+    if out is None:
+        out = torch.empty(img.shape[:-2] + (w.ncoef,), dtype=img.dtype, device=img.device)
+    ws, n = _workspace(w, None, img, batch)
+    check(fn, getattr(load(), fn)(w.c, _dtype_code(img), batch, _ptr(img), _ptr(_dev(out)),
+                                   _ptr(ws), n, _stream(img)))
+    return out
+
+
+def wavelet_synth(w: WaveletSpec, coef: torch.Tensor, out=None) -> torch.Tensor:
+    """W coef (synthesis)."""
+    return _coef_to_img("wavelet_synth", w, coef, out)
+
+
+def wavelet_synth_adjoint(w: WaveletSpec, img: torch.Tensor, out=None) -> torch.Tensor:
+    """W^* img (true adjoint, eq. 2)."""
+    return _img_to_coef("wavelet_synth_adjoint", w, img, out)
+
+
+def wavelet_analysis(w: WaveletSpec, img: torch.Tensor, out=None) -> torch.Tensor:
+    """W^dagger img (analysis)."""
+    return _img_to_coef("aw_wavelet_analysis", w, img, out)
+
+
+def wavelet_analysis_adjoint(w: WaveletSpec, coef: torch.Tensor, out=None) -> torch.Tensor:
+    """(W^dagger)^* coef (synthesis with a summing fold)."""
+    return _coef_to_img("aw_wavelet_analysis_adjoint", w, coef, out)
+
+
+# -------------------------------------------------------------- blur ops
+def _blur_call(fn, b: BlurSpec, x: torch.Tensor, out=None):
+    _dev(x)
+    batch = _batch_img(x, b.rows, b.cols)
+    if out is None:
+        out = torch.empty_like(x)
+    check(fn, getattr(load(), fn)(b.c, _dtype_code(x), batch, _ptr(x), _ptr(_dev(out)),
+                                   _stream(x)))
+    return out
+
+
+def blur(b: BlurSpec, x: torch.Tensor, out=None) -> torch.Tensor:
+    """R x."""
+    return _blur_call("blur", b, x, out)
+
+
+def blur_adjoint(b: BlurSpec, y: torch.Tensor, out=None) -> torch.Tensor:
+    """R^* y."""
+    return _blur_call("blur_adjoint", b, y, out)
+
+
+# -------------------------------------------------------------- A, A^*
+def apply_A(w: WaveletSpec, b: BlurSpec, coef: torch.Tensor, out=None) -> torch.Tensor:
+    _dev(coef)
+    batch = _batch_coef(coef, w.ncoef)
+    if out is None:
+        out = torch.empty(coef.shape[:-1] + (w.rows, w.cols), dtype=coef.dtype, device=coef.device)
+    ws, n = _workspace(w, b, coef, batch)
+    check("aw_apply_A", load().aw_apply_A(w.c, b.c, _dtype_code(coef), batch, _ptr(coef),
+                                          _ptr(_dev(out)), _ptr(ws), n, _stream(coef)))
+    return out
+
+
+def apply_A_adjoint(w: WaveletSpec, b: BlurSpec, img: torch.Tensor, out=None) -> torch.Tensor:
+    _dev(img)
+    batch = _batch_img(img, w.rows, w.cols)
+    if out is None:
+        out = torch.empty(img.shape[:-2] + (w.ncoef,), dtype=img.dtype, device=img.device)
+    ws, n = _workspace(w, b, img, batch)
+    check("aw_apply_A_adjoint", load().aw_apply_A_adjoint(w.c, b.c, _dtype_code(img), batch,
+                                                          _ptr(img), _ptr(_dev(out)), _ptr(ws), n,
+                                                          _stream(img)))
+    return out
+
+
+# ------------------------------------------------------------------ FISTA
+class FistaState:
+    """Device buffers and counters of one FISTA run (x, y coefficient
+    tensors, residual image, objective partials)."""
+
+    def __init__(self, w: WaveletSpec, b: BlurSpec, b_obs: torch.Tensor, x0=None):
+        _dev(b_obs)
+        self.w, self.b = w, b
+        self.batch = _batch_img(b_obs, w.rows, w.cols)
+        lead = b_obs.shape[:-2]
+        self.x = (torch.zeros(lead + (w.ncoef,), dtype=b_obs.dtype, device=b_obs.device)
+                  if x0 is None else x0.clone().contiguous())
+        self.y = self.x.clone()
+        self.resid = torch.empty_like(b_obs)
+        self.obj = torch.zeros(self.batch, 2, dtype=torch.float64, device=b_obs.device)
+        self.k = 1
+        self.t = 1.0
+        self.ws, self.ws_n = _workspace(w, b, b_obs, self.batch)
+
+    def c_state(self):
+        s = _lib.FistaState()
+        s.x, s.y, s.resid = self.x.data_ptr(), self.y.data_ptr(), self.resid.data_ptr()
+        s.obj = self.obj.data_ptr()
+        s.k, s.t = self.k, self.t
+        return s
+
+
+def fista_step(state: FistaState, b_obs: torch.Tensor, lam: float, L: float = 1.0,
+               want_objective: bool = False) -> None:
+    """One FISTA iteration on the state (in place)."""
+    cs = state.c_state()
+    check("fista_step", load().fista_step(state.w.c, state.b.c, _dtype_code(b_obs), state.batch,
+                                          _ptr(_dev(b_obs)), float(L), float(lam),
+                                          ctypes.byref(cs), int(bool(want_objective)),
+                                          _ptr(state.ws), state.ws_n, _stream(b_obs)))
+    state.k, state.t = int(cs.k), float(cs.t)
+
+
+# -------------------------------------------------------- conv adjoint pair
+def conv_adjoint_pair(h: torch.Tensor, s: torch.Tensor, x_obs: torch.Tensor | None = None,
+                      need_grad_h: bool = True, need_grad_s: bool = True):
+    """(resid, grad_h, grad_s) of f = 1/2 ||h * s - x_obs||^2 for a batch of
+    pairs; h: [B, K], s: [B, N], x_obs: [B, K+N-1]."""
+    _dev(h)
+    _dev(s)
+    if h.dim() == 1:
+        h, s = h[None], s[None]
+        x_obs = x_obs[None] if x_obs is not None else None
+    B, K = h.shape
+    N = s.shape[1]
+    if s.shape[0] != B or s.dtype != h.dtype:
+        raise ValueError("h and s must share batch and dtype")
+    if x_obs is not None and (tuple(x_obs.shape) != (B, K + N - 1) or x_obs.dtype != h.dtype):
+        raise ValueError("x_obs must be [B, K+N-1] of the same dtype")
+    resid = torch.empty(B, K + N - 1, dtype=h.dtype, device=h.device)
+    gh = torch.empty_like(h) if need_grad_h else None
+    gs = torch.empty_like(s) if need_grad_s else None
+    check("conv_adjoint_pair", load().conv_adjoint_pair(
+        _dtype_code(h), B, K, N, _ptr(h), _ptr(s), _ptr(_dev(x_obs)) if x_obs is not None else None,
+        _ptr(resid), _ptr(gh), _ptr(gs), _stream(h)))
+    return resid, gh, gs

@@ -1,0 +1,282 @@
+"""GPU parity of every C-ABI operator against the FP64 CPU oracle.
+
+Tolerances (relative L2 per application): 1e-5 in FP32, 1e-12 in FP64; the
+dot-product test |<Ax,y> - <x,A*y>| / (||Ax|| ||y||) <= 1e-6 with inner
+products taken in FP64 from the FP32 device outputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blur as obl
+from oracle import conv as ocv
+from oracle import filters as ofl
+from oracle import fista as ofi
+from oracle import wavelet as owv
+from paper_1707_02018_amd import ops
+from workloads import gen_conv_pair, gen_image, gen_noise, rng_for
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-5, torch.float64: 1e-12}
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(x, dt):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def dot_test(fwd_x, x, adj_y, y):
+    """Relative adjoint mismatch with FP64 inner products."""
+    lhs = np.vdot(fwd_x.ravel(), y.ravel())
+    rhs = np.vdot(x.ravel(), adj_y.ravel())
+    return abs(lhs - rhs) / (np.linalg.norm(fwd_x) * np.linalg.norm(y))
+
+
+WAVE_CASES = []
+for mode in ("zpd", "sym", "per", "per_ext"):
+    for L in (2, 8, 16):
+        for rows, cols, J in [(37, 53, 2), (64, 96, 3), (200, 136, 3), (5, 9, 1), (2, 4, 1),
+                              (130, 70, 4)]:
+            if mode == "per" and (rows % 2 ** J or cols % 2 ** J):
+                continue
+            WAVE_CASES.append((mode, L, rows, cols, J))
+
+
+@pytest.mark.parametrize("mode,L,rows,cols,J", WAVE_CASES)
+def test_wavelet_ops_parity(mode, L, rows, cols, J):
+    print(f"[wavelet] mode={mode} L={L} {rows}x{cols} J={J}", flush=True)
+    h = ofl.by_taps(L)
+    rng = rng_for(1, rows * 1000 + cols * 10 + L + J)
+    batch = 2
+    n = owv.layout(rows, cols, L, mode, J)[0]
+    x = rng.standard_normal((batch, n))
+    y = rng.standard_normal((batch, rows, cols))
+    refs = {
+        "W": owv.W(x, h, mode, J, rows, cols),
+        "Wadj": owv.W_adj(y, h, mode, J),
+        "Wpinv": owv.W_pinv(y, h, mode, J),
+        "Wpinv_adj": owv.W_pinv_adj(x, h, mode, J, rows, cols),
+    }
+    w = ops.WaveletSpec(rows, cols, J, lo=h, bc=mode)
+    for dt in (torch.float32, torch.float64):
+        xd, yd = dev(x, dt), dev(y, dt)
+        got = {
+            "W": host(ops.wavelet_synth(w, xd)),
+            "Wadj": host(ops.wavelet_synth_adjoint(w, yd)),
+            "Wpinv": host(ops.wavelet_analysis(w, yd)),
+            "Wpinv_adj": host(ops.wavelet_analysis_adjoint(w, xd)),
+        }
+        for k in refs:
+            e = rel(got[k], refs[k])
+            assert e <= TOL[dt], f"{k} {dt}: rel err {e:.3e}"
+        xr, yr = host(xd), host(yd)  # inputs as the device saw them
+        assert dot_test(got["W"], xr, got["Wadj"], yr) <= 1e-6
+        assert dot_test(got["Wpinv"], yr, got["Wpinv_adj"], xr) <= 1e-6
+
+
+BLUR_CASES = [(rows, cols, r) for rows, cols in [(37, 53), (200, 136), (5, 9), (64, 64)]
+              for r in (0, 1, 4, 7, 12)]
+
+
+@pytest.mark.parametrize("rows,cols,r", BLUR_CASES)
+def test_blur_parity(rows, cols, r):
+    print(f"[blur] {rows}x{cols} r={r}", flush=True)
+    rng = rng_for(2, rows * 100 + cols + r)
+    x = rng.standard_normal((2, rows, cols))
+    for taps in (obl.gaussian_taps(max(r, 1) / 2.0, r), rng.uniform(0.0, 1.0, 2 * r + 1)):
+        b = ops.BlurSpec(rows, cols, taps=taps)
+        ref_f, ref_a = obl.R(x, taps), obl.R_adj(x, taps)
+        for dt in (torch.float32, torch.float64):
+            xd = dev(x, dt)
+            f = host(ops.blur(b, xd))
+            a = host(ops.blur_adjoint(b, xd))
+            assert rel(f, ref_f) <= TOL[dt]
+            assert rel(a, ref_a) <= TOL[dt]
+            xr = host(xd)
+            assert dot_test(f, xr, a, xr) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["sym", "zpd", "per", "per_ext"])
+def test_A_parity_small_config(mode):
+    """256x256, db4, J=3, 9x9 Gaussian sigma=2: each A / A^* application."""
+    print(f"[A] 256x256 db4 J=3 r=4 mode={mode}", flush=True)
+    rows = cols = 256
+    h = ofl.by_taps(8)
+    psf = obl.gaussian_taps(2.0, 4)
+    prob = ofi.Problem(rows, cols, h, mode, 3, psf)
+    rng = rng_for(3, 0)
+    x = rng.standard_normal(prob.ncoef)
+    y = gen_image(rng, rows, cols)
+    ref_f, ref_a = prob.A(x), prob.A_adj(y)
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc=mode)
+    b = ops.BlurSpec(rows, cols, taps=psf)
+    for dt in (torch.float32, torch.float64):
+        xd, yd = dev(x, dt), dev(y, dt)
+        f = host(ops.apply_A(w, b, xd))
+        a = host(ops.apply_A_adjoint(w, b, yd))
+        assert rel(f, ref_f) <= TOL[dt]
+        assert rel(a, ref_a) <= TOL[dt]
+        assert dot_test(f, host(xd), a, host(yd)) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["sym", "per", "zpd"])
+def test_full_size_operators(mode):
+    """2048x2048, db4, J=4, 15x15 Gaussian sigma=3, FP32, launch shapes of
+    the benchmark: W, W^*, R, R^* against the oracle on the whole output."""
+    print(f"[full] 2048x2048 db4 J=4 r=7 mode={mode}", flush=True)
+    rows = cols = 2048
+    h = ofl.by_taps(8)
+    psf = obl.gaussian_taps(3.0, 7)
+    rng = rng_for(4, 0)
+    n = owv.layout(rows, cols, 8, mode, 4)[0]
+    x = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    img = gen_image(rng, rows, cols).astype(np.float32).astype(np.float64)
+    w = ops.WaveletSpec(rows, cols, 4, lo=h, bc=mode)
+    b = ops.BlurSpec(rows, cols, taps=psf)
+    dt = torch.float32
+    assert rel(host(ops.wavelet_synth(w, dev(x, dt))), owv.W(x, h, mode, 4, rows, cols)) <= 1e-5
+    assert rel(host(ops.wavelet_synth_adjoint(w, dev(img, dt))), owv.W_adj(img, h, mode, 4)) <= 1e-5
+    if mode == "sym":
+        assert rel(host(ops.blur(b, dev(img, dt))), obl.R(img, psf)) <= 1e-5
+        assert rel(host(ops.blur_adjoint(b, dev(img, dt))), obl.R_adj(img, psf)) <= 1e-5
+
+
+def _cfg1(dt_seed=0):
+    rows = cols = 256
+    h = ofl.by_taps(8)
+    psf = obl.gaussian_taps(2.0, 4)
+    rng = rng_for(1, dt_seed)
+    img = gen_image(rng, rows, cols)
+    b = obl.R(img, psf) + gen_noise(rng, img.shape)
+    return rows, cols, h, psf, b
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_fista_step_from_oracle_state(dt):
+    """One FISTA iteration from an identical state (k = 5)."""
+    print(f"[fista step] 256x256 {dt}", flush=True)
+    rows, cols, h, psf, b = _cfg1()
+    prob = ofi.Problem(rows, cols, h, "sym", 3, psf)
+    rng = rng_for(5, 0)
+    x_prev = rng.standard_normal(prob.ncoef) * 1e-2
+    y = rng.standard_normal(prob.ncoef) * 1e-2
+    lam, k = 2e-5, 5
+    t = 1.0
+    for _ in range(k - 1):
+        t = ofi.t_next(t)
+    beta = (t - 1.0) / ofi.t_next(t)
+    x_ref, y_ref = ofi.fista_step(prob, x_prev, y, b, beta, lam)
+    r_ref = prob.A(y) - b
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
+    bs = ops.BlurSpec(rows, cols, taps=psf)
+    bt = dev(b, dt)
+    st = ops.FistaState(w, bs, bt, x0=dev(x_prev, dt))
+    st.y.copy_(dev(y, dt))
+    st.k, st.t = k, t
+    ops.fista_step(st, bt, lam, want_objective=True)
+    tol = TOL[dt]
+    assert rel(host(st.x), x_ref) <= tol
+    assert rel(host(st.y), y_ref) <= tol
+    assert rel(host(st.resid), r_ref) <= tol
+    obj = host(st.obj)[0]
+    assert abs(obj[0] - 0.5 * np.sum(r_ref ** 2)) <= tol * 0.5 * np.sum(r_ref ** 2)
+    assert abs(obj[1] - np.sum(np.abs(x_ref))) <= tol * np.sum(np.abs(x_ref))
+    assert st.k == k + 1 and abs(st.t - ofi.t_next(t)) < 1e-15
+
+
+def test_fista_trajectory_small_config():
+    """200 iterations from zero at 256x256 (FP64 and FP32): objective
+    F(x_k) of the device iterates against the oracle's at k = 10, 50, 100, 200."""
+    print("[fista trajectory] 256x256 200 iterations", flush=True)
+    rows, cols, h, psf, b = _cfg1()
+    prob = ofi.Problem(rows, cols, h, "sym", 3, psf)
+    lam = 2e-5
+    checks = (10, 50, 100, 200)
+    F_ref = {}
+    ofi.fista(prob, b, lam, 200,
+              callback=lambda k, x: F_ref.__setitem__(k, ofi.objective(prob, x, b, lam))
+              if k in checks else None)
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
+    bs = ops.BlurSpec(rows, cols, taps=psf)
+    for dt, tol in ((torch.float64, 1e-9), (torch.float32, 1e-4)):
+        bt = dev(b, dt)
+        st = ops.FistaState(w, bs, bt)
+        for k in range(1, 201):
+            ops.fista_step(st, bt, lam)
+            if k in checks:
+                F = ofi.objective(prob, host(st.x), b, lam)
+                assert abs(F - F_ref[k]) <= tol * F_ref[k], (dt, k, F, F_ref[k])
+
+
+def test_fista_step_deterministic():
+    rows, cols, h, psf, b = _cfg1()
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
+    bs = ops.BlurSpec(rows, cols, taps=psf)
+    bt = dev(b, torch.float32)
+    outs = []
+    for _ in range(2):
+        st = ops.FistaState(w, bs, bt)
+        for _ in range(5):
+            ops.fista_step(st, bt, 2e-5, want_objective=True)
+        torch.cuda.synchronize()
+        outs.append((st.x.clone(), st.y.clone(), st.obj.clone()))
+    for a, b_ in zip(outs[0], outs[1]):
+        assert torch.equal(a, b_)
+
+
+@pytest.mark.parametrize("K,N,batch", [(3, 5, 1), (17, 1000, 3), (128, 5000, 2), (1, 7, 2),
+                                       (300, 40, 2)])
+def test_conv_pair_parity(K, N, batch):
+    print(f"[conv] K={K} N={N} batch={batch}", flush=True)
+    rng = rng_for(4, K * 7 + N)
+    hs = [gen_conv_pair(rng, K, N) for _ in range(batch)]
+    h = np.stack([p[0] for p in hs])
+    s = np.stack([p[1] for p in hs])
+    x = rng.standard_normal((batch, K + N - 1))
+    for xo in (x, None):
+        r_ref, gh_ref, gs_ref = ocv.conv_adjoint_pair(h, s, xo)
+        for dt in (torch.float32, torch.float64):
+            r, gh, gs = ops.conv_adjoint_pair(dev(h, dt), dev(s, dt),
+                                              dev(xo, dt) if xo is not None else None)
+            assert rel(host(r), r_ref) <= TOL[dt]
+            assert rel(host(gh), gh_ref) <= TOL[dt]
+            assert rel(host(gs), gs_ref) <= TOL[dt]
+
+
+def test_conv_pair_full_size_sampled():
+    """256 pairs, K = 128, N = 65536, FP32 (the benchmark shape); the oracle
+    recomputes 4 sampled pairs in full."""
+    print("[conv full] 256 x (128, 65536)", flush=True)
+    B, K, N = 256, 128, 65536
+    rng = rng_for(4, 0)
+    h = rng.standard_normal((B, K))
+    s = rng.standard_normal((B, N))
+    r, gh, gs = ops.conv_adjoint_pair(dev(h, torch.float32), dev(s, torch.float32), None)
+    r, gh, gs = host(r), host(gh), host(gs)
+    h32 = h.astype(np.float32).astype(np.float64)
+    s32 = s.astype(np.float32).astype(np.float64)
+    for p in (0, 77, 128, 255):
+        r_ref, gh_ref, gs_ref = ocv.conv_adjoint_pair(h32[p], s32[p], None)
+        assert rel(r[p], r_ref[0]) <= 1e-5
+        assert rel(gh[p], gh_ref[0]) <= 1e-5
+        assert rel(gs[p], gs_ref[0]) <= 1e-5
