@@ -1,0 +1,221 @@
+"""Benchmark: FISTA on eq. (1) at 2048 x 2048 on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--bc sym|per|zpd]
+
+A step is one FISTA iteration (one A = R W and one A^* = W^* R^*
+application plus the proximal/momentum update) on a 2048 x 2048 FP32 image:
+4-level Daubechies-4 W with symmetric boundaries, 15 x 15 Gaussian PSF
+(sigma = 3) with reflexive boundaries, lambda = 2e-5, synthetic
+rectangles-plus-gradient image with N(0, 1e-3^2) noise. The headline value is
+image Mpix per second through A and A^* (one of each per step).
+
+Also reported: Mpix/s of W, W^*, R, R^*, A, A^* alone (graph-replayed, HIP
+events), iterations to 1e-4 relative objective and the time to reach it, the
+dominant kernel against the HBM roofline, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s for A and A* at 2048²; FISTA time-to-1e-4 rel objective, plain vs warm"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--bc", default="sym", choices=["sym", "per", "zpd"])
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-target", action="store_true", help="skip the time-to-1e-4 run")
+    return ap.parse_args()
+
+
+def cpu_baseline(size: int, bc: str, iters: int = 2) -> dict:
+    """The FP64 NumPy oracle timed on this host (separate process), a bounded
+    sample of the same workload: `iters` FISTA iterations at full size."""
+    code = f"""
+import sys, time, json
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from oracle import blur as bl, filters as fl, fista as fi
+from workloads import gen_image, gen_noise, rng_for
+rng = rng_for(2, 0)
+img = gen_image(rng, {size}, {size})
+psf = bl.gaussian_taps(3.0, 7)
+b = bl.R(img, psf) + gen_noise(rng, img.shape)
+prob = fi.Problem({size}, {size}, fl.by_taps(8), {bc!r}, 4, psf)
+t0 = time.perf_counter()
+fi.fista(prob, b, 2e-5, {iters})
+dt = time.perf_counter() - t0
+print(json.dumps({{"sec_per_iter": dt / {iters}}}))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if out.returncode != 0:
+        return {"error": out.stderr[-500:]}
+    spi = json.loads(out.stdout.strip().splitlines()[-1])["sec_per_iter"]
+    return {"value": size * size / spi / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FISTA iterations (one A and one A* each) at {size}x{size}, "
+                      f"FP64 NumPy, single thread; {spi:.2f} s/iteration"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(each image is independent; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1707_02018_amd import _lib, ops
+    from workloads import gen_image, gen_noise, rng_for
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, J, lam = args.size, 4, 2e-5
+    w = ops.WaveletSpec(N, N, J, taps=8, bc=args.bc)
+    bsp = ops.BlurSpec(N, N, sigma=3.0, radius=7)
+    ncoef = w.ncoef
+    npix = N * N
+    rng = rng_for(2, 0)
+    img = torch.tensor(gen_image(rng, N, N), dtype=torch.float32, device=dev)
+    noise = torch.tensor(gen_noise(rng, (N, N)), dtype=torch.float32, device=dev)
+    b = ops.blur(bsp, img) + noise
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------- headline
+    st = ops.FistaState(w, bsp, b)
+    for _ in range(args.warmup):
+        ops.fista_step(st, b, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ops.fista_step(st, b, lam)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = npix * args.steps / dt / 1e6
+
+    # ------------------------------------------- per-operator graph timings
+    lib = _lib.load()
+    stream = torch.cuda.Stream(device=dev)
+    x = torch.randn(ncoef, device=dev) * 1e-2
+    y = torch.randn(N, N, device=dev)
+    out_img = torch.empty(N, N, device=dev)
+    out_coef = torch.empty(ncoef, device=dev)
+    wsn = ops.workspace_bytes(w, bsp, torch.float32, 1)
+    ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
+    w1 = ops.WaveletSpec(N, N, 1, taps=8, bc=args.bc)  # level 1 alone: one kernel
+    P = lambda t: ops._ptr(t)  # noqa: E731
+
+    def make_calls(s):
+        sp = __import__("ctypes").c_void_p(s.cuda_stream)
+        return {
+            "W": lambda: lib.wavelet_synth(w.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
+            "W*": lambda: lib.wavelet_synth_adjoint(w.c, 0, 1, P(y), P(out_coef), P(ws), wsn, sp),
+            "R": lambda: lib.blur(bsp.c, 0, 1, P(y), P(out_img), sp),
+            "R*": lambda: lib.blur_adjoint(bsp.c, 0, 1, P(y), P(out_img), sp),
+            "A": lambda: lib.aw_apply_A(w.c, bsp.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
+            "A*": lambda: lib.aw_apply_A_adjoint(w.c, bsp.c, 0, 1, P(y), P(out_coef), P(ws), wsn,
+                                                 sp),
+            "W*_level1": lambda: lib.wavelet_synth_adjoint(w1.c, 0, 1, P(y), P(out_coef), P(ws),
+                                                           wsn, sp),
+            "W_level1": lambda: lib.wavelet_synth(w1.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
+        }
+
+    reps = 50
+    op_us = {}
+    with torch.cuda.stream(stream):
+        calls = make_calls(stream)
+        for name, fn in calls.items():
+            for _ in range(3):
+                assert fn() == 0, name
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for _ in range(reps):
+                    fn()
+            g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(4):
+                g.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            op_us[name] = 1e3 * e0.elapsed_time(e1) / (4 * reps)
+    ops_mpix = {k: round(npix / v, 1) for k, v in op_us.items()}
+
+    # dominant single-kernel operator: level-1 analysis (W^* at level 1) or R / R^*
+    _, sr, sc = w.layout()
+    k1 = sr[1] * sc[1]
+    alg_bytes = {"W*_level1": 4 * (npix + 4 * k1), "W_level1": 4 * (npix + 4 * k1),
+                 "R": 8 * npix, "R*": 8 * npix}
+    dom = max(alg_bytes, key=lambda k: op_us[k])
+    achieved = alg_bytes[dom] / (op_us[dom] * 1e-6) / 1e9
+    kernel_names = {"W*_level1": "ana_level_kernel<float,8,SYM>",
+                    "W_level1": "synth_level_kernel<float,8,SYM>",
+                    "R": "blur_kernel<float>", "R*": "blur_adj_kernel<float>"}
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kernel_names[dom], "algorithmic_bytes": alg_bytes[dom],
+                "avg_us": round(op_us[dom], 3)}
+
+    # ------------------------------------------------ time to 1e-4 (plain)
+    target = None
+    if not args.no_target:
+        st2 = ops.FistaState(w, bsp, b)
+        obj = torch.empty(1, 3, dtype=torch.float64, device=dev)
+        Fs = []
+        every, total = 5, 3000
+        for k in range(1, total + 1):
+            ops.fista_step(st2, b, lam)
+            if k % every == 0:
+                ops.objective(w, bsp, b, st2.x, lam, out=obj)
+                Fs.append((k, obj[0, 2].item()))
+        F_star = min(F for _, F in Fs)
+        k_hit = next((k for k, F in Fs if (F - F_star) / F_star <= 1e-4), None)
+        target = {"F_star": F_star, "F_star_from": f"min F over {total} plain iterations",
+                  "iters_to_1e-4": k_hit, "checked_every": every,
+                  "time_to_1e-4_ms": round(k_hit * ms_per_step, 3) if k_hit else None}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(N, args.bc)
+
+    rec = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fista_{N}x{N}_db4_J4_{args.bc}_psf15_sigma3",
+                   "image": [N, N], "levels": J, "filter_taps": 8, "bc": args.bc,
+                   "psf_radius": 7, "psf_sigma": 3.0, "lambda": lam, "ncoef": ncoef,
+                   "batch": 1},
+        "fista_iters_per_s": round(1e3 / ms_per_step, 1),
+        "ops_us": {k: round(v, 3) for k, v in op_us.items()},
+        "ops_mpix_s": ops_mpix,
+        "roofline": roofline,
+        "time_to_target": target,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

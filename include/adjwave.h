@@ -193,6 +193,13 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
                      int32_t want_objective, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* Objective of eq. (1) at x: obj[3i] = 1/2 ||A x_i - b_i||^2,
+ * obj[3i+1] = ||x_i||_1, obj[3i+2] = obj[3i] + lambda obj[3i+1]
+ * (obj: device doubles [batch][3]; fixed-order reductions, reproducible). */
+aw_status aw_objective(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                       const void* b_obs, double lambda, const void* x, double* obj,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------- convolution adjoints */
 
 /* Blind-channel pair (Sec. "Example 2"), `batch` independent (h, s) pairs:

@@ -555,6 +555,39 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   return ok();
 }
 
+aw_status aw_objective(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                       const void* b_obs, double lambda, const void* x, double* obj,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = op_common(w, b, dtype, batch, b_obs, (void*)x, workspace, workspace_bytes, p, d, l);
+  if (st != AW_OK) return st;
+  if (!obj) return fail(AW_EINVAL, "obj is NULL");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
+  hipStream_t s = (hipStream_t)stream;
+  const int dtype_i = dtype == AW_F64;
+  void* img = wsp(workspace, l.img_off);
+  void* res = wsp(workspace, l.grad_off);  // ncoef >= rows*cols: holds one image
+  double* pr = reinterpret_cast<double*>(wsp(workspace, l.pr_off));
+  double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
+  if ((st = run_synthesis(p, dtype, batch, x, img, workspace, l, 1, s)) != AW_OK) return st;
+  if ((st = hip_check(aw::launch_blur(dtype_i, d, batch, img, res, b_obs, pr, s), "blur launch")) !=
+      AW_OK)
+    return st;
+  if ((st = hip_check(aw::launch_l1_partials(dtype_i, batch, p.ncoef, x, pl, s), "l1 launch")) !=
+      AW_OK)
+    return st;
+  if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, obj, 3, 0, s),
+                      "reduce launch")) != AW_OK)
+    return st;
+  if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pl, pl, 1.0, obj, 3, 1, s),
+                      "reduce launch")) != AW_OK)
+    return st;
+  st = hip_check(aw::launch_objective_finalize(batch, lambda, obj, s), "finalize launch");
+  return st == AW_OK ? ok() : st;
+}
+
 aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N, const void* h,
                             const void* s, const void* x_obs, void* resid, void* grad_h,
                             void* grad_s, void* stream) {

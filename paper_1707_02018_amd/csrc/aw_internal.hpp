@@ -168,6 +168,11 @@ hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad
                              double inv_L, double thresh, double beta, double* partials,
                              hipStream_t s);
 int fista_prox_blocks(long long n);
+// Per-block FP64 partials of ||x||_1 (same block count as the prox update).
+hipError_t launch_l1_partials(int dtype, int batch, long long n, const void* x, double* partials,
+                              hipStream_t s);
+// obj[i*3 + 2] = obj[i*3] + lambda * obj[i*3 + 1]
+hipError_t launch_objective_finalize(int batch, double lambda, double* obj, hipStream_t s);
 // out[i*out_stride + out_off] = scale * sum_j partials[i][j] (fixed order).
 hipError_t launch_reduce_partials(int batch, int nparts, const double* partials, double scale,
                                   double* out, int out_stride, int out_off, hipStream_t s);

@@ -67,6 +67,49 @@ hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(kProxThreads) void l1_partials_kernel(long long n, const T* __restrict__ x,
+                                                                   double* __restrict__ partials) {
+  __shared__ double red[kProxThreads];
+  const T* X = x + (long long)blockIdx.y * n;
+  double l1 = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T v = X[i];
+    l1 += (double)(v < T(0) ? -v : v);
+  }
+  red[threadIdx.x] = l1;
+  __syncthreads();
+  for (int s = kProxThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+hipError_t launch_l1_partials(int dtype, int batch, long long n, const void* x, double* partials,
+                              hipStream_t s) {
+  dim3 grid(fista_prox_blocks(n), batch);
+  if (dtype)
+    hipLaunchKernelGGL(l1_partials_kernel<double>, grid, dim3(kProxThreads), 0, s, n,
+                       static_cast<const double*>(x), partials);
+  else
+    hipLaunchKernelGGL(l1_partials_kernel<float>, grid, dim3(kProxThreads), 0, s, n,
+                       static_cast<const float*>(x), partials);
+  return hipGetLastError();
+}
+
+__global__ void objective_finalize_kernel(int batch, double lambda, double* obj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < batch) obj[3 * i + 2] = obj[3 * i] + lambda * obj[3 * i + 1];
+}
+
+hipError_t launch_objective_finalize(int batch, double lambda, double* obj, hipStream_t s) {
+  hipLaunchKernelGGL(objective_finalize_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, batch,
+                     lambda, obj);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int nparts, const double* __restrict__ p,
                                                               double scale, double* __restrict__ out,
                                                               int out_stride, int out_off) {

@@ -279,6 +279,21 @@ def fista_step(state: FistaState, b_obs: torch.Tensor, lam: float, L: float = 1.
     state.k, state.t = int(cs.k), float(cs.t)
 
 
+def objective(w: WaveletSpec, b: BlurSpec, b_obs: torch.Tensor, x: torch.Tensor, lam: float,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    """[batch, 3] FP64 device tensor: 1/2||Ax-b||^2, ||x||_1, F(x) (eq. 1)."""
+    _dev(b_obs)
+    _dev(x)
+    batch = _batch_img(b_obs, w.rows, w.cols)
+    if out is None:
+        out = torch.empty(batch, 3, dtype=torch.float64, device=x.device)
+    ws, n = _workspace(w, b, x, batch)
+    check("aw_objective", load().aw_objective(w.c, b.c, _dtype_code(x), batch, _ptr(b_obs),
+                                              float(lam), _ptr(x), _ptr(out), _ptr(ws), n,
+                                              _stream(x)))
+    return out
+
+
 # -------------------------------------------------------- conv adjoint pair
 def conv_adjoint_pair(h: torch.Tensor, s: torch.Tensor, x_obs: torch.Tensor | None = None,
                       need_grad_h: bool = True, need_grad_s: bool = True):
