@@ -147,7 +147,10 @@ WsLayout layout_ws(const WavePlan* p, const aw::BlurDesc* b, aw_dtype dt, int ba
       off = align_up(off + (size_t)p->sr[j] * p->sc[j] * batch * ts);
     }
     l.ext_off = off;
-    if (p->bc == aw::PER_EXT) {
+    bool need_ext = p->bc == aw::PER_EXT;
+    for (int j = 1; j <= p->J; ++j)
+      if (p->bc == aw::SYM && (p->sr[j - 1] < p->e || p->sc[j - 1] < p->e)) need_ext = true;
+    if (need_ext) {
       size_t mx = 0;
       for (int j = 1; j <= p->J; ++j) {
         const size_t m = (size_t)(p->sr[j - 1] + 2 * p->e) * (p->sc[j - 1] + 2 * p->e);
@@ -199,7 +202,12 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
     d.bc = p.bc;
     d.pinv = pinv;
     hipError_t e;
-    if (p.bc == aw::PER_EXT) {
+    // the tile kernel folds with closed-form preimages, valid when every
+    // extended sample is at most one reflection away (N >= e); periodic
+    // extension and shorter signals materialise the extended level and fold it
+    const bool two_step = p.bc == aw::PER_EXT ||
+                          (p.bc == aw::SYM && (p.sr[j - 1] < p.e || p.sc[j - 1] < p.e));
+    if (two_step) {
       // extended synthesis (zero-boundary core on length N + 2e), then fold
       aw::SynthLevel z = d;
       z.bc = aw::ZPD;

@@ -36,13 +36,19 @@ __host__ __device__ inline int posmod(int a, int b) {
 // ---------------------------------------------------------------------------
 // Extension index maps.
 
-// Source sample of extended position i in [-e, N+e).
+// Source sample of extended position i in [-e, N+e). When N >= e every
+// extended sample is at most one reflection (or one period) away, which the
+// closed forms cover; shorter signals take the general index arithmetic.
 __host__ __device__ inline int src_index(int i, int N, int bc) {
   if (bc == SYM) {
-    int j = posmod(i, 2 * N);
+    if (i >= -N && i < 2 * N) return i < 0 ? -1 - i : (i >= N ? 2 * N - 1 - i : i);
+    const int j = posmod(i, 2 * N);
     return j < N ? j : 2 * N - 1 - j;
   }
-  if (bc == PER_EXT) return posmod(i, N);
+  if (bc == PER_EXT) {
+    if (i >= -N && i < 2 * N) return i < 0 ? i + N : (i >= N ? i - N : i);
+    return posmod(i, N);
+  }
   return i;
 }
 
@@ -55,7 +61,19 @@ __host__ __device__ inline int for_each_preimage(int p, int N, int e, int bc, F&
     f(p + e);
     return 1;
   }
-  int cnt = 0;
+  int cnt = 1;
+  if (N >= e) {  // at most one extra preimage on each side
+    f(p + e);
+    if (bc == SYM) {
+      if (p < e) { f(e - 1 - p); ++cnt; }
+      if (p >= N - e) { f(2 * N - 1 - p + e); ++cnt; }
+    } else {
+      if (p < e) { f(p + N + e); ++cnt; }
+      if (p >= N - e) { f(p - N + e); ++cnt; }
+    }
+    return cnt;
+  }
+  cnt = 0;
   if (bc == SYM) {
     const int P = 2 * N;
     for (int fam = 0; fam < 2; ++fam) {

@@ -1,212 +1,244 @@
-// Separable Gaussian blur R with half-point reflexive boundaries and its
-// structural adjoint R^* (Sec. "Example 1"), gfx950.
+// Separable blur R with half-point reflexive boundaries and its structural
+// adjoint R^* (Sec. "Example 1"), gfx950.
 //
-// R: a workgroup owns a TR x TC output tile, gathers the (TR+2r) x (TC+2r)
-// input window through the reflexive index map into LDS, filters along
-// columns, then rows. Optional epilogue for FISTA: subtract the observation b
-// and emit a deterministic per-tile FP64 partial of 1/2 ||R x - b||^2.
+// With the reflexive extension x^[q] = x[refl(q)], one dimension reads
+//   (R x)[p]   = sum_u g[u] x^[p - u]                       (convolution)
+//   (R^* y)[p] = sum_{m : refl(m) = p} sum_u g[u] y[m + u]  (correlation on the
+//                extended domain, halo folded back onto its preimages).
+// Writing the folded terms against the reflected window q = p - r + k, a
+// sample reached through an even number of reflections (every sample inside
+// the image) carries the correlation tap g[k - r], one reached through an odd
+// number carries the convolution tap g[r - k]. So
+//   (R^* y)[p] = sum_k t[k] y^[q] + sum_{k : q odd} (t[2r - k] - t[k]) y^[q],
+// with t the correlation taps: the reflected window of R plus a correction on
+// the at most r reflected samples of border outputs, which vanishes for a
+// symmetric PSF (then R^* = R).
 //
-// R^*: correlation with the taps on the extended domain m in [-r, N+r),
-// followed by the fold of the halo onto its reflexive preimages. Edge tiles
-// widen their window to the reflected preimages (same rule as the wavelet
-// fold), so interior tiles run the plain correlation.
+// A workgroup owns a TR x TC output tile and stages the reflected
+// (TR+2r) x (TC+2r) window in LDS: interior tiles with 16-byte loads, border
+// tiles through per-row / per-column reflection tables. The column pass writes
+// TR+2r rows of TC filtered values (VW outputs per thread from 16-byte LDS
+// reads); the row pass walks each column in chunks of four outputs. An optional
+// epilogue subtracts b and emits deterministic per-tile FP64 partials of
+// 1/2 ||R x - b||^2 for FISTA.
 #include "aw_internal.hpp"
 
 namespace aw {
 
 template <typename T>
-struct BlurTile;
+struct BlurCfg;
 template <>
-struct BlurTile<float> {
-  static constexpr int TR = 32, TC = 64;
+struct BlurCfg<float> {
+  static constexpr int TR = 64, TC = 64, VW = 4, NT = 512;
+  using V = float4;
 };
 template <>
-struct BlurTile<double> {
-  static constexpr int TR = 16, TC = 64;
+struct BlurCfg<double> {
+  static constexpr int TR = 32, TC = 32, VW = 2, NT = 512;
+  using V = double2;
 };
 
 template <typename T>
 struct BlurArgs {
-  int rows, cols, radius;
-  T taps[2 * kMaxRadius + 1];
+  int rows, cols;
+  int symmetric;               // taps symmetric: the R^* border correction vanishes
+  T taps[2 * kMaxRadius + 1];  // correlation order: out[p] = sum_k t[k] in[p - r + k]
 };
 
-template <typename T>
-static BlurArgs<T> make_blur_args(const BlurDesc& b) {
-  BlurArgs<T> a{};
-  a.rows = b.rows;
-  a.cols = b.cols;
-  a.radius = b.radius;
-  for (int i = 0; i < 2 * b.radius + 1; ++i) a.taps[i] = (T)b.taps[i];
-  return a;
-}
-
-__device__ inline int refl(int m, int N) {
+__device__ inline int refl_idx(int m, int N) {
+  if (m >= -N && m < 2 * N) return m < 0 ? -1 - m : (m >= N ? 2 * N - 1 - m : m);
   const int j = posmod(m, 2 * N);
   return j < N ? j : 2 * N - 1 - j;
 }
 
-// Deterministic block sum of one double per thread (fixed tree order).
-__device__ inline double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  return red[0];
+// position m of the reflexive extension reached through an odd number of
+// reflections (orientation reversed)
+__device__ inline bool refl_odd(int m, int N) {
+  if (m >= -N && m < 2 * N) return m < 0 || m >= N;
+  return (floordiv(m, N) & 1) != 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a, const T* __restrict__ X,
-                                                   T* __restrict__ Yout,
-                                                   const T* __restrict__ SUB,
-                                                   double* __restrict__ partials) {
-  constexpr int TR = BlurTile<T>::TR, TC = BlurTile<T>::TC;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  __shared__ T staps[2 * kMaxRadius + 1];
-  __shared__ double red[256];
+template <typename T, int R, bool ADJ>
+__global__ __launch_bounds__(BlurCfg<T>::NT) void blur_tile_kernel(BlurArgs<T> a, const T* __restrict__ X,
+                                                        T* __restrict__ Y,
+                                                        const T* __restrict__ SUB,
+                                                        double* __restrict__ partials) {
+  using Cfg = BlurCfg<T>;
+  using V = typename Cfg::V;
+  constexpr int TR = Cfg::TR, TC = Cfg::TC, VW = Cfg::VW, NT = Cfg::NT;
+  constexpr int WR = TR + 2 * R;                       // window rows
+  constexpr int WC = TC + 2 * R;                       // window cols
+  constexpr int SXS = ((WC + VW - 1) / VW) * VW + VW;  // sx row stride (vector aligned)
+  constexpr int NV = (VW + 2 * R + VW - 1) / VW;       // vectors read per column-pass item
+  constexpr int K = 2 * R + 1;
+  __shared__ __align__(16) T sx[WR * SXS];
+  __shared__ __align__(16) T sh[WR * TC];
+  __shared__ int rtab[WR], ctab[WC];
+  __shared__ double red[NT];
 
+  const int N = a.rows, M = a.cols;
   const int img = blockIdx.z;
-  const int N = a.rows, Mc = a.cols, r = a.radius;
-  const int r0 = blockIdx.y * TR, r1 = min(r0 + TR, N);
-  const int c0 = blockIdx.x * TC, c1 = min(c0 + TC, Mc);
-  const int nr = r1 - r0, nc = c1 - c0;
-  const int wr = nr + 2 * r, wc = nc + 2 * r;
-  T* sx = smem;            // [wr][wc]
-  T* sh = smem + wr * wc;  // [wr][TC]
-  if (threadIdx.x < 2 * r + 1) staps[threadIdx.x] = a.taps[threadIdx.x];
-
-  const long long plane = (long long)N * Mc;
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * TC;
+  const long long plane = (long long)N * M;
   const T* Xi = X + img * plane;
-  for (int idx = threadIdx.x; idx < wr * wc; idx += blockDim.x) {
-    const int i = idx / wc;
-    const int j = idx - i * wc;
-    sx[idx] = Xi[(long long)refl(r0 - r + i, N) * Mc + refl(c0 - r + j, Mc)];
-  }
-  __syncthreads();
-  // along columns: sh[i][pc] = sum_v g[v] x[i][pc - v]
-  for (int idx = threadIdx.x; idx < wr * nc; idx += blockDim.x) {
-    const int i = idx / nc;
-    const int pc = idx - i * nc;
-    const T* row = sx + i * wc + pc + r;
-    T acc = T(0);
-    for (int v = -r; v <= r; ++v) acc += staps[v + r] * row[-v];
-    sh[i * TC + pc] = acc;
-  }
-  __syncthreads();
-  double part = 0.0;
-  T* Yi = Yout + img * plane;
-  for (int idx = threadIdx.x; idx < nr * nc; idx += blockDim.x) {
-    const int pr = idx / nc;
-    const int pc = idx - pr * nc;
-    const T* col = sh + (pr + r) * TC + pc;
-    T acc = T(0);
-    for (int u = -r; u <= r; ++u) acc += staps[u + r] * col[-u * TC];
-    const long long off = (long long)(r0 + pr) * Mc + (c0 + pc);
-    if (SUB) {
-      acc -= SUB[img * plane + off];
-      part += 0.5 * (double)acc * (double)acc;
+  T t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = a.taps[k];
+
+  const bool interior = (r0 >= R) && (r0 + TR + R <= N) && (c0 >= R) && (c0 + TC + R <= M);
+
+  // 1. stage the reflected window: rows r0-R .. r0+TR+R, cols c0-R .. c0+TC+R
+  constexpr int RA = ((R + VW - 1) / VW) * VW;  // aligned left halo
+  constexpr int WCV = (TC + 2 * RA) / VW;       // aligned vectors per window row
+  if (interior && (M % VW) == 0) {
+    constexpr int NVEC = WR * WCV;
+    constexpr int IT = (NVEC + NT - 1) / NT;
+    V buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NVEC) {
+        const int i = idx / WCV, jv = idx - (idx / WCV) * WCV;
+        buf[it] = *reinterpret_cast<const V*>(Xi + (long long)(r0 - R + i) * M + (c0 - RA) + jv * VW);
+      }
     }
-    Yi[off] = acc;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NVEC) {
+        const int i = idx / WCV, jv = idx - (idx / WCV) * WCV;
+        const T* e = reinterpret_cast<const T*>(&buf[it]);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          const int j = jv * VW + u - (RA - R);  // window column
+          if (j >= 0 && j < WC) sx[i * SXS + j] = e[u];
+        }
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < WR; i += NT) rtab[i] = refl_idx(r0 - R + i, N);
+    for (int j = threadIdx.x; j < WC; j += NT) ctab[j] = refl_idx(c0 - R + j, M);
+    __syncthreads();
+    constexpr int IT = (WR * WC + NT - 1) / NT;  // every load issued before any LDS write
+    T v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < WR * WC) {
+        const int i = idx / WC, j = idx - (idx / WC) * WC;
+        v[it] = Xi[(long long)rtab[i] * M + ctab[j]];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < WR * WC) {
+        const int i = idx / WC, j = idx - (idx / WC) * WC;
+        sx[i * SXS + j] = v[it];
+      }
+    }
+  }
+  for (int idx = threadIdx.x; idx < WR * (SXS - WC); idx += NT) {  // vector padding
+    const int i = idx / (SXS - WC), j = idx - (idx / (SXS - WC)) * (SXS - WC);
+    sx[i * SXS + WC + j] = T(0);
+  }
+  __syncthreads();
+
+  // 2. filter along columns: sh[i][pc] = sum_k t[k] sx[i][pc + k]
+  constexpr int QV = TC / VW;
+  for (int item = threadIdx.x; item < WR * QV; item += NT) {
+    const int i = item / QV, q = item - (item / QV) * QV;
+    const T* row = sx + i * SXS + q * VW;
+    T w[NV * VW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const V vv = *reinterpret_cast<const V*>(row + v * VW);
+      const T* e = reinterpret_cast<const T*>(&vv);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) w[v * VW + u] = e[u];
+    }
+    V ov;
+    T* o = reinterpret_cast<T*>(&ov);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += t[k] * w[u + k];
+      o[u] = acc;
+    }
+    *reinterpret_cast<V*>(sh + i * TC + q * VW) = ov;
+  }
+  const bool fix = ADJ && !interior && !a.symmetric;
+  if (fix) {  // R^* border columns: odd-reflection samples take the convolution tap
+    __syncthreads();
+    for (int item = threadIdx.x; item < WR * TC; item += NT) {
+      const int i = item / TC, pc = item - (item / TC) * TC;
+      const int p = c0 + pc;
+      if (p >= M || (p >= R && p < M - R)) continue;
+      T acc = T(0);
+#pragma unroll 1
+      for (int k = 0; k < K; ++k)
+        if (refl_odd(p - R + k, M)) acc += (a.taps[K - 1 - k] - a.taps[k]) * sx[i * SXS + pc + k];
+      sh[i * TC + pc] += acc;
+    }
+  }
+  __syncthreads();
+
+  // 3. filter along rows: each thread owns one column and RB output rows,
+  //    walked in chunks of four
+  constexpr int RG = NT / TC;  // row groups
+  constexpr int RB = TR / RG;  // rows per thread
+  constexpr int CR = RB < 4 ? RB : 4;
+  const int pc = threadIdx.x % TC;
+  const int rg = threadIdx.x / TC;
+  const int p_c = c0 + pc;
+  T* Yi = Y + img * plane;
+  double part = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < RB; c += CR) {
+    const int lr = rg * RB + c;  // first output row of the chunk (window row offset)
+    T hw[CR + 2 * R];
+#pragma unroll
+    for (int i = 0; i < CR + 2 * R; ++i) hw[i] = sh[(lr + i) * TC + pc];
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += t[k] * hw[i + k];
+      const int p_r = r0 + lr + i;
+      if (fix && (p_r < R || p_r >= N - R)) {
+#pragma unroll 1
+        for (int k = 0; k < K; ++k)
+          if (refl_odd(p_r - R + k, N))
+            acc += (a.taps[K - 1 - k] - a.taps[k]) * sh[(lr + i + k) * TC + pc];
+      }
+      if (p_r < N && p_c < M) {
+        const long long off = (long long)p_r * M + p_c;
+        if (SUB) {
+          acc -= SUB[img * plane + off];
+          part += 0.5 * (double)acc * (double)acc;
+        }
+        Yi[off] = acc;
+      }
+    }
   }
   if (partials) {
-    const double s = block_sum(part, red);
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
     if (threadIdx.x == 0)
-      partials[(long long)img * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = s;
+      partials[(long long)img * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
+          red[0];
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void blur_adj_kernel(BlurArgs<T> a, const T* __restrict__ Y,
-                                                       T* __restrict__ Xout) {
-  constexpr int TR = BlurTile<T>::TR, TC = BlurTile<T>::TC;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  __shared__ T staps[2 * kMaxRadius + 1];
-
-  const int img = blockIdx.z;
-  const int N = a.rows, Mc = a.cols, r = a.radius;
-  const int r0 = blockIdx.y * TR, r1 = min(r0 + TR, N);
-  const int c0 = blockIdx.x * TC, c1 = min(c0 + TC, Mc);
-  int nlo_r, nhi_r, nlo_c, nhi_c;  // windows in n = m + r (m extended index)
-  fold_window(r0, r1, N, r, nlo_r, nhi_r);
-  fold_window(c0, c1, Mc, r, nlo_c, nhi_c);
-  // y window: rows [nlo_r - 2r, nhi_r), cols [nlo_c - 2r, nhi_c)
-  const int yo_r = nlo_r - 2 * r, yo_c = nlo_c - 2 * r;
-  const int wyr = nhi_r - yo_r, wyc = nhi_c - yo_c;
-  const int nc = c1 - c0, nr = r1 - r0;
-  T* sy = smem;              // [wyr][wyc]
-  T* sz = smem + wyr * wyc;  // [wyr][TC] correlated along columns + column fold
-  if (threadIdx.x < 2 * r + 1) staps[threadIdx.x] = a.taps[threadIdx.x];
-
-  const long long plane = (long long)N * Mc;
-  const T* Yi = Y + img * plane;
-  for (int idx = threadIdx.x; idx < wyr * wyc; idx += blockDim.x) {
-    const int i = idx / wyc;
-    const int j = idx - i * wyc;
-    const int yr = yo_r + i, yc = yo_c + j;
-    sy[idx] = (yr >= 0 && yr < N && yc >= 0 && yc < Mc) ? Yi[(long long)yr * Mc + yc] : T(0);
-  }
-  __syncthreads();
-  // sz[i][pc] = sum_{m: refl(m) = c0+pc} sum_v g[v] y[i][m + v]
-  for (int idx = threadIdx.x; idx < wyr * nc; idx += blockDim.x) {
-    const int i = idx / nc;
-    const int pc = idx - i * nc;
-    const T* row = sy + i * wyc;
-    T acc = T(0);
-    for_each_preimage(c0 + pc, Mc, r, SYM, [&](int n) {
-      const T* p = row + (n - nlo_c) + r;  // y column (n - r) + v, v in [-r, r]
-      for (int v = -r; v <= r; ++v) acc += staps[v + r] * p[v];
-    });
-    sz[i * TC + pc] = acc;
-  }
-  __syncthreads();
-  T* Xi = Xout + img * plane;
-  for (int idx = threadIdx.x; idx < nr * nc; idx += blockDim.x) {
-    const int pr = idx / nc;
-    const int pc = idx - pr * nc;
-    T acc = T(0);
-    for_each_preimage(r0 + pr, N, r, SYM, [&](int n) {
-      const T* p = sz + ((n - nlo_r) + r) * TC + pc;
-      for (int u = -r; u <= r; ++u) acc += staps[u + r] * p[u * TC];
-    });
-    Xi[(long long)(r0 + pr) * Mc + (c0 + pc)] = acc;
-  }
-}
-
-template <typename T>
-static size_t blur_lds(const BlurDesc& b) {
-  constexpr int TR = BlurTile<T>::TR, TC = BlurTile<T>::TC;
-  const int r = b.radius;
-  const int wr = TR + 2 * r, wc = TC + 2 * r;
-  return sizeof(T) * (size_t)(wr * wc + wr * TC);
-}
-
-static int adj_max_window(int N, int r, int tile) {
-  int mx = 0;
-  for (int p0 = 0; p0 < N; p0 += tile) {
-    const int p1 = p0 + tile < N ? p0 + tile : N;
-    int nlo, nhi;
-    fold_window(p0, p1, N, r, nlo, nhi);
-    if (nhi - nlo + 2 * r > mx) mx = nhi - nlo + 2 * r;
-  }
-  return mx;
-}
-
-template <typename T>
-static size_t blur_adj_lds(const BlurDesc& b) {
-  constexpr int TR = BlurTile<T>::TR, TC = BlurTile<T>::TC;
-  const int wyr = adj_max_window(b.rows, b.radius, TR);
-  const int wyc = adj_max_window(b.cols, b.radius, TC);
-  return sizeof(T) * (size_t)(wyr * wyc + wyr * TC);
 }
 
 template <typename T>
 static dim3 blur_grid(const BlurDesc& b, int batch) {
-  return dim3((b.cols + BlurTile<T>::TC - 1) / BlurTile<T>::TC,
-              (b.rows + BlurTile<T>::TR - 1) / BlurTile<T>::TR, batch);
+  return dim3((b.cols + BlurCfg<T>::TC - 1) / BlurCfg<T>::TC,
+              (b.rows + BlurCfg<T>::TR - 1) / BlurCfg<T>::TR, batch);
 }
 
 int blur_tiles(int dtype, const BlurDesc& b) {
@@ -214,46 +246,52 @@ int blur_tiles(int dtype, const BlurDesc& b) {
   return (int)(g.x * g.y);
 }
 
-template <typename T>
-static hipError_t set_lds(const void* kern, size_t lds) {
-  if (lds > 64 * 1024)
-    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
+template <typename T, bool ADJ>
+static BlurArgs<T> make_args(const BlurDesc& b) {
+  BlurArgs<T> a{};
+  a.rows = b.rows;
+  a.cols = b.cols;
+  const int K = 2 * b.radius + 1;
+  a.symmetric = 1;
+  for (int k = 0; k < K; ++k)
+    if (b.taps[k] != b.taps[K - 1 - k]) a.symmetric = 0;
+  // R: out[p] = sum_v g[v] x[p - v] -> correlation taps reversed; R^*: as given
+  for (int k = 0; k < K; ++k) a.taps[k] = (T)(ADJ ? b.taps[k] : b.taps[K - 1 - k]);
+  return a;
 }
 
-template <typename T>
-static hipError_t launch_blur_t(const BlurDesc& b, int batch, const void* x, void* y,
-                                const void* sub, double* partials, hipStream_t s) {
-  const size_t lds = blur_lds<T>(b);
-  hipError_t e = set_lds<T>((const void*)blur_kernel<T>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(blur_kernel<T>, blur_grid<T>(b, batch), dim3(256), lds, s,
-                     make_blur_args<T>(b), static_cast<const T*>(x), static_cast<T*>(y),
+template <typename T, int R, bool ADJ>
+static hipError_t launch_r(const BlurDesc& b, int batch, const void* x, void* y, const void* sub,
+                           double* partials, hipStream_t s) {
+  hipLaunchKernelGGL((blur_tile_kernel<T, R, ADJ>), blur_grid<T>(b, batch), dim3(BlurCfg<T>::NT), 0, s,
+                     make_args<T, ADJ>(b), static_cast<const T*>(x), static_cast<T*>(y),
                      static_cast<const T*>(sub), partials);
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_blur_adj_t(const BlurDesc& b, int batch, const void* y, void* x,
-                                    hipStream_t s) {
-  const size_t lds = blur_adj_lds<T>(b);
-  hipError_t e = set_lds<T>((const void*)blur_adj_kernel<T>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(blur_adj_kernel<T>, blur_grid<T>(b, batch), dim3(256), lds, s,
-                     make_blur_args<T>(b), static_cast<const T*>(y), static_cast<T*>(x));
-  return hipGetLastError();
+template <typename T, bool ADJ>
+static hipError_t launch_t(const BlurDesc& b, int batch, const void* x, void* y, const void* sub,
+                           double* partials, hipStream_t s) {
+  switch (b.radius) {
+#define AW_R(r) \
+  case r: return launch_r<T, r, ADJ>(b, batch, x, y, sub, partials, s);
+    AW_R(0) AW_R(1) AW_R(2) AW_R(3) AW_R(4) AW_R(5) AW_R(6) AW_R(7) AW_R(8) AW_R(9) AW_R(10)
+    AW_R(11) AW_R(12)
+#undef AW_R
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_blur(int dtype, const BlurDesc& b, int batch, const void* x, void* y,
                        const void* sub, double* partials, hipStream_t s) {
-  return dtype ? launch_blur_t<double>(b, batch, x, y, sub, partials, s)
-               : launch_blur_t<float>(b, batch, x, y, sub, partials, s);
+  return dtype ? launch_t<double, false>(b, batch, x, y, sub, partials, s)
+               : launch_t<float, false>(b, batch, x, y, sub, partials, s);
 }
 
 hipError_t launch_blur_adjoint(int dtype, const BlurDesc& b, int batch, const void* y, void* x,
                                hipStream_t s) {
-  return dtype ? launch_blur_adj_t<double>(b, batch, y, x, s)
-               : launch_blur_adj_t<float>(b, batch, y, x, s);
+  return dtype ? launch_t<double, true>(b, batch, y, x, nullptr, nullptr, s)
+               : launch_t<float, true>(b, batch, y, x, nullptr, nullptr, s);
 }
 
 }  // namespace aw

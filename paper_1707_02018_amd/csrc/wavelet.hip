@@ -13,6 +13,8 @@
 // the extended input window (extension index map and 1/mult weights applied
 // during the gather), filters along columns into LDS, then along rows, and
 // writes a, H, V, D.
+#include <type_traits>
+
 #include "aw_internal.hpp"
 
 namespace aw {
@@ -31,11 +33,24 @@ template <typename T>
 struct AnaTile;
 template <>
 struct AnaTile<float> {
-  static constexpr int TKR = 16, TKC = 32;
+  static constexpr int TKR = 32, TKC = 32, NT = 512;
 };
 template <>
 struct AnaTile<double> {
-  static constexpr int TKR = 16, TKC = 32;
+  static constexpr int TKR = 16, TKC = 32, NT = 512;
+};
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  using V2 = float2;
+  using V4 = float4;
+};
+template <>
+struct Vec<double> {
+  using V2 = double2;
+  using V4 = double4;
 };
 
 template <typename T>
@@ -49,107 +64,266 @@ static Taps<T> make_taps(const double* lo, int L) {
 }
 
 // ---------------------------------------------------------------- synthesis
+// Column-direction synthesis value of extended position n (any parity) from
+// the staged coefficient window; lo = a/H pair, hi = V/D pair.
+template <typename T, int L, int BC, typename V4>
+__device__ inline void synth_col_any(const V4* sc, int nkc, int j, int kw, int n, const Taps<T>& f,
+                                     T& lo, T& hi) {
+  const int base = synth_k0(n, L, BC) - kw;
+  const bool odd = n & 1;
+#pragma unroll
+  for (int m = 0; m < L / 2; ++m) {
+    const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
+    const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
+    const V4 q = sc[(base - m) * nkc + j];
+    lo += q.x * fh;
+    lo += q.y * fg;
+    hi += q.z * fh;
+    hi += q.w * fg;
+  }
+}
+
+template <typename T, int L, int BC, typename V2>
+__device__ inline T synth_row_any(const V2* row, int kw, int n, const Taps<T>& f) {
+  const int base = synth_k0(n, L, BC) - kw;
+  const bool odd = n & 1;
+  T acc = T(0);
+#pragma unroll
+  for (int m = 0; m < L / 2; ++m) {
+    const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
+    const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
+    const V2 q = row[base - m];
+    acc += q.x * fh;
+    acc += q.y * fg;
+  }
+  return acc;
+}
+
+// Split of a tile [p0, p1) (p0 even) into output pairs (p0 + 2s, p0 + 2s + 1):
+// pairs [sL, sR) are regular (single preimage p + e, both rows inside the
+// tile); the rows before 2 sL and from 2 sR on are handled one by one
+// (border rows within e of an edge, and a ragged last row). nsp counts them.
+__device__ inline void special_range(int p0, int p1, int N, int e, bool shift, int& sL, int& sR,
+                                     int& nsp) {
+  const int np = (p1 - p0 + 1) / 2;
+  sL = shift && e > p0 ? (e - p0 + 1) / 2 : 0;
+  if (sL > np) sL = np;
+  const int m = shift ? min(N - e, p1) : p1;
+  int r = (m - 1 - p0 + 1) / 2;  // ceil((m - 1 - p0) / 2) for m - 1 - p0 >= 0
+  if (m - 1 - p0 < 0) r = 0;
+  sR = r < sL ? sL : (r > np ? np : r);
+  nsp = 2 * sL + ((p1 - p0) - 2 * sR);
+}
+
+// t-th position (tile-relative) handled one by one
+__device__ inline int special_pos(int t, int sL, int sR) {
+  return t < 2 * sL ? t : 2 * sR + (t - 2 * sL);
+}
+
 template <typename T, int L, int BC>
-__global__ __launch_bounds__(256) void synth_level_kernel(SynthLevel d, Taps<T> f) {
+__global__ __launch_bounds__(512) void synth_level_kernel(SynthLevel d, Taps<T> f) {
   constexpr int TR = SynthTile<T>::TR, TC = SynthTile<T>::TC;
+  constexpr int HL = L / 2;
+  // extended modes shift the signal by e = L - 1 (odd): the first row of a
+  // pair has odd n and the second row uses the next coefficient row
+  constexpr bool SHIFT = (BC == SYM);
+  using V2 = typename Vec<T>::V2;
+  using V4 = typename Vec<T>::V4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
 
   const int img = blockIdx.z;
   const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
-  const int er = (BC == SYM) ? d.r.e : 0;
-  const int ec = (BC == SYM) ? d.c.e : 0;
+  const int er = SHIFT ? d.r.e : 0;
+  const int ec = SHIFT ? d.c.e : 0;
   const int r0 = blockIdx.y * TR, r1 = min(r0 + TR, Nr);
   const int c0 = blockIdx.x * TC, c1 = min(c0 + TC, Nc);
   int nlo_r, nhi_r, nlo_c, nhi_c;
   fold_window(r0, r1, Nr, er, nlo_r, nhi_r);
   fold_window(c0, c1, Nc, ec, nlo_c, nhi_c);
-  const int kwr = synth_k0(nlo_r, L, BC) - (L / 2 - 1);
+  const int kwr = synth_k0(nlo_r, L, BC) - (HL - 1);
   const int nkr = synth_k0(nhi_r - 1, L, BC) + 1 - kwr;
-  const int kwc = synth_k0(nlo_c, L, BC) - (L / 2 - 1);
+  const int kwc = synth_k0(nlo_c, L, BC) - (HL - 1);
   const int nkc = synth_k0(nhi_c - 1, L, BC) + 1 - kwc;
-  const int nwin = nkr * nkc;
 
-  T* sc = smem;             // [4][nkr][nkc] coefficient window: a, H, V, D
-  T* st = smem + 4 * nwin;  // [2][TR][nkc]  column-synthesised lo / hi
+  V4* sc = reinterpret_cast<V4*>(smem_raw);  // [nkr][nkc] (a, H, V, D)
+  V2* st = reinterpret_cast<V2*>(sc + nkr * nkc);  // [TR][nkc] (lo, hi) after the row fold
 
   const T* A = static_cast<const T*>(d.a) + (long long)img * d.stride_a;
   const T* HVD = static_cast<const T*>(d.hvd) + (long long)img * d.stride_hvd;
   const long long band = (long long)Kr * Kc;
 
-  // 1. stage the coefficient window (zero outside [0,K); circular wraps)
-  for (int idx = threadIdx.x; idx < 4 * nwin; idx += blockDim.x) {
-    const int b = idx / nwin;
-    const int rem = idx - b * nwin;
-    const int i = rem / nkc;
-    const int j = rem - i * nkc;
-    int kr = kwr + i, kc = kwc + j;
-    bool ok;
-    if (BC == PER) {
-      kr = posmod(kr, Kr);
-      kc = posmod(kc, Kc);
-      ok = true;
-    } else {
-      ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
+  // 1. stage the coefficient window, bands interleaved; each thread issues a
+  //    batch of loads before writing LDS
+  constexpr int CH = 4;
+  for (int base = 0; base < nkr * nkc; base += 512 * CH) {
+    V4 q[CH];
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int idx = base + threadIdx.x + it * 512;
+      q[it].x = q[it].y = q[it].z = q[it].w = T(0);
+      if (idx < nkr * nkc) {
+        const int i = idx / nkc;
+        const int j = idx - i * nkc;
+        int kr = kwr + i, kc = kwc + j;
+        bool ok;
+        if (BC == PER) {
+          kr = posmod(kr, Kr);
+          kc = posmod(kc, Kc);
+          ok = true;
+        } else {
+          ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
+        }
+        if (ok) {
+          const long long off = (long long)kr * Kc + kc;
+          q[it].x = A[off];
+          q[it].y = HVD[off];
+          q[it].z = HVD[band + off];
+          q[it].w = HVD[2 * band + off];
+        }
+      }
     }
-    T v = T(0);
-    if (ok) {
-      const long long off = (long long)kr * Kc + kc;
-      v = (b == 0) ? A[off] : HVD[(b - 1) * band + off];
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int idx = base + threadIdx.x + it * 512;
+      if (idx < nkr * nkc) sc[idx] = q[it];
     }
-    sc[idx] = v;
   }
   __syncthreads();
 
-  // 2. column-direction synthesis (along rows) with the row fold
-  const int nrows = r1 - r0;
-  for (int idx = threadIdx.x; idx < nrows * nkc; idx += blockDim.x) {
-    const int pr = idx / nkc;
-    const int j = idx - pr * nkc;
+  // 2. column-direction synthesis. Regular row pairs (single preimage, both
+  //    rows in the tile) run the paired fast path; border rows and a ragged
+  //    last row run a separate pass, so no wave mixes the two.
+  int sL, sR, nsp;
+  special_range(r0, r1, Nr, er, SHIFT, sL, sR, nsp);
+  for (int item = threadIdx.x; item < (sR - sL) * nkc; item += blockDim.x) {
+    const int s = sL + item / nkc;
+    const int j = item - (item / nkc) * nkc;
+    const int p0 = r0 + 2 * s;
+    T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
+    const int k1 = synth_k0(p0 + er, L, BC) - kwr;
+    if (SHIFT) {  // row p0: odd taps at k1; row p0+1: even taps at k1+1
+      V4 q[HL + 1];
+#pragma unroll
+      for (int m = 0; m <= HL; ++m) q[m] = sc[(k1 + 1 - m) * nkc + j];
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        lo0 += q[m + 1].x * f.h[2 * m + 1];
+        lo0 += q[m + 1].y * f.g[2 * m + 1];
+        hi0 += q[m + 1].z * f.h[2 * m + 1];
+        hi0 += q[m + 1].w * f.g[2 * m + 1];
+        lo1 += q[m].x * f.h[2 * m];
+        lo1 += q[m].y * f.g[2 * m];
+        hi1 += q[m].z * f.h[2 * m];
+        hi1 += q[m].w * f.g[2 * m];
+      }
+    } else {  // both rows share k1: even taps, then odd taps
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        const V4 q = sc[(k1 - m) * nkc + j];
+        lo0 += q.x * f.h[2 * m];
+        lo0 += q.y * f.g[2 * m];
+        hi0 += q.z * f.h[2 * m];
+        hi0 += q.w * f.g[2 * m];
+        lo1 += q.x * f.h[2 * m + 1];
+        lo1 += q.y * f.g[2 * m + 1];
+        hi1 += q.z * f.h[2 * m + 1];
+        hi1 += q.w * f.g[2 * m + 1];
+      }
+    }
+    V2 v0, v1;
+    v0.x = lo0;
+    v0.y = hi0;
+    v1.x = lo1;
+    v1.y = hi1;
+    st[(2 * s) * nkc + j] = v0;
+    st[(2 * s + 1) * nkc + j] = v1;
+  }
+  // border rows: p + e and, near an edge, the reflected preimage
+  // (e - 1 - p on the left, 2N - 1 - p + e on the right), weighted 1/mult
+  for (int item = threadIdx.x; item < nsp * nkc; item += blockDim.x) {
+    const int t = item / nkc;
+    const int j = item - t * nkc;
+    const int pr = special_pos(t, sL, sR);
+    const int p = r0 + pr;
     T lo = T(0), hi = T(0);
-    const int cnt = for_each_preimage(r0 + pr, Nr, er, BC, [&](int n) {
-      const int base = synth_k0(n, L, BC) - kwr;
-      const bool odd = n & 1;
-#pragma unroll
-      for (int m = 0; m < L / 2; ++m) {
-        const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
-        const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
-        const int row = base - m;
-        lo += sc[(0 * nkr + row) * nkc + j] * fh + sc[(1 * nkr + row) * nkc + j] * fg;
-        hi += sc[(2 * nkr + row) * nkc + j] * fh + sc[(3 * nkr + row) * nkc + j] * fg;
-      }
-    });
-    if (d.pinv && cnt > 1) {
-      const T w = T(1) / T(cnt);
-      lo *= w;
-      hi *= w;
+    int cnt = 1;
+    synth_col_any<T, L, BC>(sc, nkc, j, kwr, p + er, f, lo, hi);
+    if (SHIFT && p < er) {
+      synth_col_any<T, L, BC>(sc, nkc, j, kwr, er - 1 - p, f, lo, hi);
+      ++cnt;
     }
-    st[pr * nkc + j] = lo;
-    st[(TR + pr) * nkc + j] = hi;
+    if (SHIFT && p >= Nr - er) {
+      synth_col_any<T, L, BC>(sc, nkc, j, kwr, 2 * Nr - 1 - p + er, f, lo, hi);
+      ++cnt;
+    }
+    if (d.pinv && cnt > 1) {
+      const T wgt = cnt == 2 ? T(0.5) : T(1) / T(cnt);
+      lo *= wgt;
+      hi *= wgt;
+    }
+    V2 v;
+    v.x = lo;
+    v.y = hi;
+    st[pr * nkc + j] = v;
   }
   __syncthreads();
 
-  // 3. row-direction synthesis (along columns) with the column fold
-  const int ncols = c1 - c0;
+  // 3. row-direction synthesis, same split over columns
+  int qL, qR, nsc;
+  special_range(c0, c1, Nc, ec, SHIFT, qL, qR, nsc);
   T* O = static_cast<T*>(d.out) + (long long)img * d.stride_out;
-  for (int idx = threadIdx.x; idx < nrows * ncols; idx += blockDim.x) {
-    const int pr = idx / ncols;
-    const int pc = idx - pr * ncols;
-    const T* slo = st + pr * nkc;
-    const T* shi = st + (TR + pr) * nkc;
-    T acc = T(0);
-    const int cnt = for_each_preimage(c0 + pc, Nc, ec, BC, [&](int n) {
-      const int base = synth_k0(n, L, BC) - kwc;
-      const bool odd = n & 1;
+  constexpr int QC = TC / 2;
+  const int nrows = r1 - r0;
+  for (int item = threadIdx.x; item < nrows * QC; item += blockDim.x) {
+    const int pr = item / QC;
+    const int q = item - pr * QC;
+    if (q < qL || q >= qR) continue;
+    const int p = c0 + 2 * q;
+    const V2* row = st + pr * nkc;
+    T o0 = T(0), o1 = T(0);
+    const int k1 = synth_k0(p + ec, L, BC) - kwc;
+    if (SHIFT) {
+      V2 w[HL + 1];
 #pragma unroll
-      for (int m = 0; m < L / 2; ++m) {
-        const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
-        const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
-        acc += slo[base - m] * fh + shi[base - m] * fg;
+      for (int m = 0; m <= HL; ++m) w[m] = row[k1 + 1 - m];
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        o0 += w[m + 1].x * f.h[2 * m + 1];
+        o0 += w[m + 1].y * f.g[2 * m + 1];
+        o1 += w[m].x * f.h[2 * m];
+        o1 += w[m].y * f.g[2 * m];
       }
-    });
-    if (d.pinv && cnt > 1) acc *= T(1) / T(cnt);
-    O[(long long)(r0 + pr) * Nc + (c0 + pc)] = acc;
+    } else {
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        const V2 w = row[k1 - m];
+        o0 += w.x * f.h[2 * m];
+        o0 += w.y * f.g[2 * m];
+        o1 += w.x * f.h[2 * m + 1];
+        o1 += w.y * f.g[2 * m + 1];
+      }
+    }
+    T* orow = O + (long long)(r0 + pr) * Nc;
+    orow[p] = o0;
+    orow[p + 1] = o1;
+  }
+  for (int item = threadIdx.x; item < nrows * nsc; item += blockDim.x) {
+    const int pr = item / nsc;
+    const int t = item - pr * nsc;
+    const int p = c0 + special_pos(t, qL, qR);
+    const V2* row = st + pr * nkc;
+    T acc = synth_row_any<T, L, BC>(row, kwc, p + ec, f);
+    int cnt = 1;
+    if (SHIFT && p < ec) {
+      acc += synth_row_any<T, L, BC>(row, kwc, ec - 1 - p, f);
+      ++cnt;
+    }
+    if (SHIFT && p >= Nc - ec) {
+      acc += synth_row_any<T, L, BC>(row, kwc, 2 * Nc - 1 - p + ec, f);
+      ++cnt;
+    }
+    if (d.pinv && cnt > 1) acc *= cnt == 2 ? T(0.5) : T(1) / T(cnt);
+    O[(long long)(r0 + pr) * Nc + p] = acc;
   }
 }
 
@@ -188,7 +362,7 @@ static hipError_t launch_synth_t(const double* lo, const SynthLevel& d, int batc
   }
   dim3 grid((d.c.N + SynthTile<T>::TC - 1) / SynthTile<T>::TC,
             (d.r.N + SynthTile<T>::TR - 1) / SynthTile<T>::TR, batch);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, d, make_taps<T>(lo, L));
+  hipLaunchKernelGGL(kern, grid, dim3(512), lds, s, d, make_taps<T>(lo, L));
   return hipGetLastError();
 }
 
@@ -221,10 +395,16 @@ hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLev
 
 // ----------------------------------------------------------------- analysis
 template <typename T, int L, int BC>
-__global__ __launch_bounds__(256) void ana_level_kernel(AnaLevel d, Taps<T> f) {
-  constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
+__global__ __launch_bounds__(AnaTile<T>::NT) void ana_level_kernel(AnaLevel d, Taps<T> f) {
+  constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC, NT = AnaTile<T>::NT;
+  constexpr int NWR = 2 * TKR + L - 2, NWC = 2 * TKC + L - 2;
+  constexpr int VW = 16 / sizeof(T);                       // elements per 16-byte LDS read
+  constexpr int SUS = ((NWC + VW - 1) / VW) * VW + VW;     // input row stride
+  constexpr int NV = (2 * VW + L - 2 + VW - 1) / VW;       // vectors per pass-1 item
+  using V2 = typename Vec<T>::V2;
+  using V4 = typename Vec<T>::V4;
+  __shared__ __align__(16) T su[NWR * SUS];
+  __shared__ __align__(16) V2 slh[NWR * TKC];
 
   const int img = blockIdx.z;
   const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
@@ -233,96 +413,178 @@ __global__ __launch_bounds__(256) void ana_level_kernel(AnaLevel d, Taps<T> f) {
   const int kc0 = blockIdx.x * TKC, kc1 = min(kc0 + TKC, Kc);
   const int nlo_r = (BC == PER) ? 2 * kr0 : 2 * kr0 - L + 2;
   const int nlo_c = (BC == PER) ? 2 * kc0 : 2 * kc0 - L + 2;
-  const int nwr = 2 * (kr1 - kr0) + L - 2;
-  const int nwc = 2 * (kc1 - kc0) + L - 2;
   const int Mr = Nr + 2 * er, Mc = Nc + 2 * ec;
-
-  T* su = smem;             // [nwr][nwc] extended, weighted input window
-  T* sl = su + nwr * nwc;   // [nwr][TKC] low-pass along columns
-  T* sh = sl + nwr * TKC;   // [nwr][TKC] high-pass along columns
-
   const T* Y = static_cast<const T*>(d.in) + (long long)img * d.stride_in;
-  const bool edge_r = (BC != PER) && (nlo_r < 2 * er || nlo_r + nwr > Nr);
-  const bool edge_c = (BC != PER) && (nlo_c < 2 * ec || nlo_c + nwc > Nc);
+  const bool interior = (BC == PER) ? (nlo_r + NWR <= Nr && nlo_c + NWC <= Nc)
+                                    : (nlo_r >= 2 * er && nlo_r + NWR <= Nr && nlo_c >= 2 * ec &&
+                                       nlo_c + NWC <= Nc);
 
-  // 1. gather u(n) = w(src) y[src(n - e)] (zero outside [0, M))
-  for (int idx = threadIdx.x; idx < nwr * nwc; idx += blockDim.x) {
-    const int i = idx / nwc;
-    const int j = idx - i * nwc;
-    const int nr = nlo_r + i, nc = nlo_c + j;
-    T v = T(0);
-    if (BC == PER) {
-      v = Y[(long long)posmod(nr, Nr) * Nc + posmod(nc, Nc)];
-    } else if (nr >= 0 && nr < Mr && nc >= 0 && nc < Mc) {
-      const int sr = edge_r ? src_index(nr - er, Nr, BC) : nr - er;
-      const int scc = edge_c ? src_index(nc - ec, Nc, BC) : nc - ec;
-      v = Y[(long long)sr * Nc + scc];
-      if (d.pinv) {
-        const int m = (edge_r ? multiplicity(sr, Nr, er, BC) : 1) *
-                      (edge_c ? multiplicity(scc, Nc, ec, BC) : 1);
-        if (m > 1) v = v / T(m);
+  // 1. gather u(n) = w(src) y[src(n - e)] (zero outside [0, M)); all loads
+  //    of a thread are issued before its LDS writes
+  if (interior && (Nc % VW) == 0) {
+    const int g0 = nlo_c - ec;                  // first input column of the window
+    const int a0 = (g0 >= 0 ? g0 / VW : -((-g0 + VW - 1) / VW)) * VW;
+    const int off = g0 - a0;                    // 0 .. VW-1
+    constexpr int NVR = (NWC + 2 * VW - 2) / VW + 1;  // vectors per row (upper bound)
+    constexpr int NVEC = NWR * NVR;
+    constexpr int IT = (NVEC + NT - 1) / NT;
+    using LV = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    LV buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NVEC) {
+        const int i = idx / NVR, jv = idx - (idx / NVR) * NVR;
+        const int gc = a0 + jv * VW;
+        if (gc + VW <= Nc)
+          buf[it] = *reinterpret_cast<const LV*>(Y + (long long)(nlo_r + i - er) * Nc + gc);
       }
     }
-    su[idx] = v;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NVEC) {
+        const int i = idx / NVR, jv = idx - (idx / NVR) * NVR;
+        const int gc = a0 + jv * VW;
+        if (gc + VW <= Nc) {
+          T e[VW];
+          if constexpr (VW == 4) {
+            e[0] = buf[it].x; e[1] = buf[it].y; e[2] = buf[it].z; e[3] = buf[it].w;
+          } else {
+            e[0] = buf[it].x; e[1] = buf[it].y;
+          }
+#pragma unroll
+          for (int u = 0; u < VW; ++u) {
+            const int j = jv * VW + u - off;
+            if (j >= 0 && j < NWC) su[i * SUS + j] = e[u];
+          }
+        }
+      }
+    }
+  } else {
+    // per-row / per-column source index and weight (1/mult for W^*, 1 for
+    // W^dagger, 0 outside the extended signal), then one gather loop
+    __shared__ int rsrc[NWR], csrc[NWC];
+    __shared__ T rwt[NWR], cwt[NWC];
+    for (int i = threadIdx.x; i < NWR + NWC; i += blockDim.x) {
+      const bool isr = i < NWR;
+      const int n = isr ? nlo_r + i : nlo_c + (i - NWR);
+      const int Nn = isr ? Nr : Nc, ee = isr ? er : ec, Mm = Nn + 2 * ee;
+      int src = 0;
+      T wgt = T(0);
+      if (BC == PER) {
+        src = posmod(n, Nn);
+        wgt = T(1);
+      } else if (n >= 0 && n < Mm) {
+        src = src_index(n - ee, Nn, BC);
+        wgt = d.pinv ? T(1) / T(multiplicity(src, Nn, ee, BC)) : T(1);
+      }
+      if (isr) {
+        rsrc[i] = src;
+        rwt[i] = wgt;
+      } else {
+        csrc[i - NWR] = src;
+        cwt[i - NWR] = wgt;
+      }
+    }
+    __syncthreads();
+    constexpr int IT2 = (NWR * NWC + NT - 1) / NT;  // every load issued before any LDS write
+    T v[IT2];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NWR * NWC) {
+        const int i = idx / NWC, j = idx - (idx / NWC) * NWC;
+        v[it] = Y[(long long)rsrc[i] * Nc + csrc[j]] * (rwt[i] * cwt[j]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NWR * NWC) {
+        const int i = idx / NWC, j = idx - (idx / NWC) * NWC;
+        su[i * SUS + j] = v[it];
+      }
+    }
+  }
+  for (int idx = threadIdx.x; idx < NWR * (SUS - NWC); idx += blockDim.x) {
+    const int i = idx / (SUS - NWC), j = idx - (idx / (SUS - NWC)) * (SUS - NWC);
+    su[i * SUS + NWC + j] = T(0);
   }
   __syncthreads();
 
-  // 2. filter along columns: sl/sh[i][kk] = sum_j f[j] u(i, 2 kk + j)
-  const int nkc_t = kc1 - kc0;
-  for (int idx = threadIdx.x; idx < nwr * nkc_t; idx += blockDim.x) {
-    const int i = idx / nkc_t;
-    const int kk = idx - i * nkc_t;
-    const T* row = su + i * nwc + 2 * kk;
-    T lo = T(0), hi = T(0);
+  // 2. filter along columns, two output columns per item:
+  //    (lo, hi)[i][kc] = sum_j (h, g)[j] u(i, 2 kc + j)
+  constexpr int CP = TKC / 2;
+  for (int item = threadIdx.x; item < NWR * CP; item += blockDim.x) {
+    const int i = item / CP, cp = item - (item / CP) * CP;
+    const T* row = su + i * SUS + 4 * cp;
+    T w[NV * VW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (VW == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
+        w[4 * v] = q.x; w[4 * v + 1] = q.y; w[4 * v + 2] = q.z; w[4 * v + 3] = q.w;
+      } else {
+        const double2 q = *reinterpret_cast<const double2*>(row + 2 * v);
+        w[2 * v] = q.x; w[2 * v + 1] = q.y;
+      }
+    }
+    T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      lo += f.h[j] * row[j];
-      hi += f.g[j] * row[j];
+      lo0 += f.h[j] * w[j];
+      hi0 += f.g[j] * w[j];
+      lo1 += f.h[j] * w[j + 2];
+      hi1 += f.g[j] * w[j + 2];
     }
-    sl[i * TKC + kk] = lo;
-    sh[i * TKC + kk] = hi;
+    V4 o;
+    o.x = lo0; o.y = hi0; o.z = lo1; o.w = hi1;
+    *reinterpret_cast<V4*>(slh + i * TKC + 2 * cp) = o;
   }
   __syncthreads();
 
-  // 3. filter along rows and write the four bands
+  // 3. filter along rows: thread = column kc and KB consecutive coefficient rows
+  constexpr int RBLK = NT / TKC;
+  constexpr int KB = TKR / RBLK;
+  constexpr int NW = 2 * KB + L - 2;
+  const int kk = threadIdx.x % TKC;
+  const int rb = threadIdx.x / TKC;
+  V2 win[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) win[i] = slh[(2 * rb * KB + i) * TKC + kk];
   T* Aout = static_cast<T*>(d.a) + (long long)img * d.stride_a;
   T* HVD = static_cast<T*>(d.hvd) + (long long)img * d.stride_hvd;
   const long long band = (long long)Kr * Kc;
-  const int nkr_t = kr1 - kr0;
-  for (int idx = threadIdx.x; idx < nkr_t * nkc_t; idx += blockDim.x) {
-    const int ii = idx / nkc_t;
-    const int kk = idx - ii * nkc_t;
+  const int kc = kc0 + kk;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) {
     T a = T(0), H = T(0), V = T(0), D = T(0);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      const T l = sl[(2 * ii + j) * TKC + kk];
-      const T h = sh[(2 * ii + j) * TKC + kk];
-      a += f.h[j] * l;
-      H += f.g[j] * l;
-      V += f.h[j] * h;
-      D += f.g[j] * h;
+      const V2 q = win[2 * r + j];
+      a += f.h[j] * q.x;
+      H += f.g[j] * q.x;
+      V += f.h[j] * q.y;
+      D += f.g[j] * q.y;
     }
-    const long long off = (long long)(kr0 + ii) * Kc + (kc0 + kk);
-    Aout[off] = a;
-    HVD[off] = H;
-    HVD[band + off] = V;
-    HVD[2 * band + off] = D;
+    const int kr = kr0 + rb * KB + r;
+    if (kr < kr1 && kc < kc1) {
+      const long long off = (long long)kr * Kc + kc;
+      Aout[off] = a;
+      HVD[off] = H;
+      HVD[band + off] = V;
+      HVD[2 * band + off] = D;
+    }
   }
 }
 
 template <typename T, int L, int BC>
 static hipError_t launch_ana_t(const double* lo, const AnaLevel& d, int batch, hipStream_t s) {
   constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC;
-  const int nwr = 2 * TKR + L - 2, nwc = 2 * TKC + L - 2;
-  const size_t lds = sizeof(T) * (size_t)(nwr * nwc + 2 * nwr * TKC);
-  auto kern = ana_level_kernel<T, L, BC>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   dim3 grid((d.c.K + TKC - 1) / TKC, (d.r.K + TKR - 1) / TKR, batch);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, d, make_taps<T>(lo, L));
+  hipLaunchKernelGGL((ana_level_kernel<T, L, BC>), grid, dim3(AnaTile<T>::NT), 0, s, d,
+                     make_taps<T>(lo, L));
   return hipGetLastError();
 }
 
