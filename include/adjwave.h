@@ -200,6 +200,53 @@ aw_status aw_objective(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, in
                        const void* b_obs, double lambda, const void* x, double* obj,
                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------ batched FISTA (uneven) */
+
+/* Opaque plan for FISTA on n independent FP32 problems of uneven image size,
+ * wavelet depth, filter length and PSF (each with its own aw_wavelet /
+ * aw_blur; boundary modes zero, symmetric or circular, every level at least
+ * as long as the extension width). Creation validates and sizes; binding
+ * uploads per-stage tile queues (the plan's own device memory, freed by
+ * aw_batch_destroy). aw_batch_step then only enqueues kernels whose varying
+ * inputs live in device memory, so one iteration can be captured into a
+ * hipGraph once and replayed. */
+typedef struct aw_batch aw_batch;
+
+aw_status aw_batch_create(int32_t n, const aw_wavelet* w, const aw_blur* b, aw_batch** plan);
+aw_status aw_batch_destroy(aw_batch* plan);
+
+/* coef_off / img_off: n+1 element offsets of problem i in the concatenated
+ * coefficient / image buffers (either may be NULL); workspace bytes. */
+aw_status aw_batch_layout(const aw_batch* plan, int64_t* coef_off, int64_t* img_off,
+                          size_t* workspace_bytes);
+
+/* Tunables: cfg[0..2] tile-shape variant (0 or 1) of the synthesis, analysis
+ * and blur kernels; cfg[3] streams (1..4) over which the kernel classes of one
+ * stage run concurrently. Rebuilds the tile queues of a bound plan. */
+aw_status aw_batch_set_config(aw_batch* plan, const int32_t* cfg);
+
+/* Bind device buffers: b_obs (concatenated images), x, y (concatenated
+ * coefficients, in/out) and the workspace; FISTA step 1/L and lambda. Blocking
+ * (uploads descriptor tables and the beta_k table). */
+aw_status aw_batch_bind(aw_batch* plan, const void* b_obs, void* x, void* y, void* workspace,
+                        size_t workspace_bytes, double lambda, double L);
+
+/* Device addresses inside the bound workspace: the iteration counter k
+ * (int32), per-problem active flags (int32[n]; 0 skips every tile of that
+ * problem) and per-problem partials obj[n][3] of the last step
+ * (1/2 ||A y_k - b||^2, ||x_k||_1, ||x_k - x_{k-1}||^2). */
+aw_status aw_batch_control(const aw_batch* plan, int32_t** counter, int32_t** active,
+                           double** obj);
+
+/* k = 1, all problems active, x = y = 0 (kernels on stream). */
+aw_status aw_batch_reset(aw_batch* plan, void* stream);
+
+/* One FISTA iteration for every active problem (kernels only). */
+aw_status aw_batch_step(aw_batch* plan, void* stream);
+
+/* Message of the last failing aw_batch_* call on this thread. */
+const char* aw_batch_last_error(void);
+
 /* ------------------------------------------------- convolution adjoints */
 
 /* Blind-channel pair (Sec. "Example 2"), `batch` independent (h, s) pairs:

@@ -59,6 +59,14 @@ SIGNATURES = {
                    _P],
     "aw_objective": [_W, _B, _i32, _i32, _P, _dbl, _P, _P, _P, _sz, _P],
     "conv_adjoint_pair": [_i32, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _P],
+    "aw_batch_create": [_i32, _W, _B, ctypes.POINTER(_P)],
+    "aw_batch_destroy": [_P],
+    "aw_batch_layout": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)],
+    "aw_batch_set_config": [_P, ctypes.POINTER(_i32)],
+    "aw_batch_bind": [_P, _P, _P, _P, _P, _sz, _dbl, _dbl],
+    "aw_batch_control": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    "aw_batch_reset": [_P, _P],
+    "aw_batch_step": [_P, _P],
 }
 
 _lib = None
@@ -75,6 +83,8 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     lib.aw_last_error.restype = ctypes.c_char_p
     lib.aw_last_error.argtypes = []
+    lib.aw_batch_last_error.restype = ctypes.c_char_p
+    lib.aw_batch_last_error.argtypes = []
     for name, args in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -91,4 +101,6 @@ class AdjwaveError(RuntimeError):
 
 def check(fn: str, status: int) -> None:
     if status != OK:
-        raise AdjwaveError(fn, status, load().aw_last_error().decode())
+        lib = load()
+        msg = (lib.aw_batch_last_error() if fn.startswith("aw_batch") else lib.aw_last_error())
+        raise AdjwaveError(fn, status, msg.decode())

@@ -159,9 +159,54 @@ struct FoldLevel {
   int pinv;
 };
 
+template <typename T>
+struct SynthItem {
+  SynthLevel d;
+  Taps<T> f;
+  int image;
+};
+template <typename T>
+struct AnaItem {
+  AnaLevel d;
+  Taps<T> f;
+  int image;
+};
+
+// Item owning tile t of a batched launch: prefix[i] <= t < prefix[i+1]
+// (binary search over the n + 1 prefix entries).
+__device__ inline int find_item(const int* prefix, int n, int t) {
+  int lo = 0, hi = n;  // invariant: prefix[lo] <= t < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 struct BlurDesc {
   int rows, cols, radius;
   double taps[2 * kMaxRadius + 1];
+};
+
+template <typename T>
+struct BlurArgs {
+  int rows, cols;
+  int symmetric;               // taps symmetric: the R^* border correction vanishes
+  T taps[2 * kMaxRadius + 1];  // correlation order: out[p] = sum_k t[k] in[p - r + k]
+};
+
+template <typename T>
+struct BlurItem {
+  BlurArgs<T> a;
+  const T* x;
+  T* y;
+  const T* sub;
+  double* partials;  // per-tile slots of this image, or null
+  int image;
+  int tiles_x;
 };
 
 // Launchers (return hipSuccess or the launch error). dtype: 0 = float, 1 = double.
@@ -194,6 +239,27 @@ hipError_t launch_objective_finalize(int batch, double lambda, double* obj, hipS
 // out[i*out_stride + out_off] = scale * sum_j partials[i][j] (fixed order).
 hipError_t launch_reduce_partials(int batch, int nparts, const double* partials, double scale,
                                   double* out, int out_stride, int out_off, hipStream_t s);
+
+// Batched (tile-queue) launches; items / prefix are device arrays.
+int synth_tiles(int dtype, int var, const SynthLevel& d);
+int ana_tiles(int dtype, int var, const AnaLevel& d);
+size_t synth_item_lds(int dtype, int L, int var, const SynthLevel& d);
+size_t synth_item_size(int dtype);
+size_t ana_item_size(int dtype);
+size_t blur_item_size(int dtype);
+void make_synth_item(int dtype, const SynthLevel& d, const double* lo, int L, int image, void* out);
+void make_ana_item(int dtype, const AnaLevel& d, const double* lo, int L, int image, void* out);
+int blur_tiles_var(int dtype, int var, const BlurDesc& b, int* tiles_x);
+void make_blur_item(int dtype, bool adj, const BlurDesc& b, const void* x, void* y, const void* sub,
+                    double* partials, int image, int tiles_x, void* out);
+hipError_t launch_synth_batch(int dtype, int L, int bc, int var, const void* items,
+                              const int* prefix, int n, int total, const int* active, size_t lds,
+                              hipStream_t s);
+hipError_t launch_ana_batch(int dtype, int L, int bc, int var, const void* items,
+                            const int* prefix, int n, int total, const int* active, hipStream_t s);
+hipError_t launch_blur_batch(int dtype, int radius, bool adj, int var, const void* items,
+                             const int* prefix, int n, int total, const int* active,
+                             hipStream_t s);
 
 hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, const void* s,
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,

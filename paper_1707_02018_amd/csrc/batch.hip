@@ -1,0 +1,644 @@
+// Batched FISTA over images of uneven size, depth, filter and PSF.
+//
+// A plan fixes n problems; binding device buffers builds, per pipeline stage,
+// a tile queue per kernel class (filter length x boundary mode for the wavelet
+// levels, PSF radius for the blur): descriptor items plus a prefix of tile
+// counts, uploaded once. One iteration enqueues, for every stage, one launch
+// per class over all tiles of all images of that class:
+//   W levels J..1 -> R(.) - b (+ residual partials) -> R^* -> W^* levels 1..J
+//   -> proximal/momentum update (beta_k from a device table indexed by a
+//   device iteration counter) -> per-image objective partials -> counter++.
+// Classes of one stage are independent and run on forked streams. Nothing is
+// allocated, copied or synchronised per iteration and every kernel reads its
+// varying inputs from device memory, so an iteration can be captured once into
+// a hipGraph and replayed. Images whose active flag is 0 skip all their tiles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aw_internal.hpp"
+
+namespace aw {
+
+template <typename T, bool ADJ>
+BlurArgs<T> make_blur_args(const BlurDesc& b);
+
+// ------------------------------------------------------------ device kernels
+constexpr int kBatchProxThreads = 256;
+constexpr int kBatchProxChunk = kBatchProxThreads * 16;
+
+struct ProxItem {
+  long long off;  // coefficient offset of the image
+  long long n;    // coefficients of the image
+  int image;
+};
+
+// x_k = soft(y - g / L, lambda / L); y_{k+1} = x_k + beta_k (x_k - x_{k-1});
+// per-block FP64 partials of ||x_k||_1 and ||x_k - x_{k-1}||^2.
+template <typename T>
+__global__ __launch_bounds__(kBatchProxThreads) void batch_prox_kernel(
+    const ProxItem* __restrict__ items, const int* __restrict__ prefix, int n,
+    const int* __restrict__ active, const T* __restrict__ grad, T* __restrict__ x,
+    T* __restrict__ y, double inv_L, double thresh, const double* __restrict__ beta_tab,
+    int beta_len, const int* __restrict__ counter, double* __restrict__ l1_part,
+    double* __restrict__ dx_part) {
+  __shared__ double red[2][kBatchProxThreads];
+  const int i = find_item(prefix, n, blockIdx.x);
+  const ProxItem it = items[i];
+  double l1 = 0.0, dx = 0.0;
+  if (!active || active[it.image]) {
+    int k = *counter;
+    k = k < 1 ? 1 : (k > beta_len ? beta_len : k);
+    const T beta = (T)beta_tab[k - 1];
+    const T il = (T)inv_L, th = (T)thresh;
+    const long long b0 = (long long)(blockIdx.x - prefix[i]) * kBatchProxChunk;
+    const long long e0 = b0 + kBatchProxChunk < it.n ? b0 + kBatchProxChunk : it.n;
+    for (long long j = b0 + threadIdx.x; j < e0; j += kBatchProxThreads) {
+      const long long o = it.off + j;
+      const T v = y[o] - grad[o] * il;
+      const T xn = v > th ? v - th : (v < -th ? v + th : T(0));
+      const T xo = x[o];
+      y[o] = xn + beta * (xn - xo);
+      x[o] = xn;
+      l1 += (double)(xn < T(0) ? -xn : xn);
+      dx += (double)(xn - xo) * (double)(xn - xo);
+    }
+  }
+  red[0][threadIdx.x] = l1;
+  red[1][threadIdx.x] = dx;
+  __syncthreads();
+  for (int s = kBatchProxThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    l1_part[blockIdx.x] = red[0][0];
+    dx_part[blockIdx.x] = red[1][0];
+  }
+}
+
+// obj[i] = {1/2 ||A y - b||^2, ||x||_1, ||x_k - x_{k-1}||^2}: fixed-order sums
+// over the image's tile and block ranges; inactive images keep their values.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(
+    int n, const int* __restrict__ tile_prefix, const double* __restrict__ r_part,
+    const int* __restrict__ blk_prefix, const double* __restrict__ l1_part,
+    const double* __restrict__ dx_part, const int* __restrict__ active, double* __restrict__ obj) {
+  __shared__ double red[3][256];
+  const int i = blockIdx.x;
+  if (i >= n || (active && !active[i])) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int t = tile_prefix[i] + threadIdx.x; t < tile_prefix[i + 1]; t += 256) a += r_part[t];
+  for (int t = blk_prefix[i] + threadIdx.x; t < blk_prefix[i + 1]; t += 256) {
+    b += l1_part[t];
+    c += dx_part[t];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) obj[3 * i + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void batch_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+}
+
+// counter = 1, active = 1, x = y = 0 (fill kernels, capture-safe)
+template <typename T>
+__global__ void batch_reset_kernel(int* counter, int* active, int n, T* x, T* y, long long ncoef) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) counter[0] = 1;
+  if (i < n) active[i] = 1;
+  for (long long j = i; j < ncoef; j += (long long)gridDim.x * blockDim.x) {
+    x[j] = T(0);
+    y[j] = T(0);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_batch_prox(const ProxItem* items, const int* prefix, int n, int total,
+                             const int* active, const float* grad, float* x, float* y,
+                             double inv_L, double thresh, const double* beta_tab, int beta_len,
+                             const int* counter, double* l1_part, double* dx_part,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(batch_prox_kernel<float>, dim3(total), dim3(kBatchProxThreads), 0, s, items,
+                     prefix, n, active, grad, x, y, inv_L, thresh, beta_tab, beta_len, counter,
+                     l1_part, dx_part);
+  return hipGetLastError();
+}
+
+}  // namespace aw
+
+// =================================================================== plan
+#include "../../include/adjwave.h"
+
+namespace {
+
+constexpr int kBetaLen = 1 << 17;  // beta_k for k <= 131072 (clamped beyond)
+constexpr size_t kAlignB = 256;
+size_t alignb(size_t x) { return (x + kAlignB - 1) / kAlignB * kAlignB; }
+
+struct Image {
+  aw_wavelet w;
+  aw::BlurDesc b;
+  int J, L, bc, e, rows, cols;
+  int sr[AW_MAX_LEVELS + 1], sc[AW_MAX_LEVELS + 1];
+  long long ncoef, npix;
+  long long off_hvd[AW_MAX_LEVELS + 1];
+  // workspace offsets (bytes)
+  size_t a_off[AW_MAX_LEVELS + 1], tmp_off, res_off;
+};
+
+struct Group {        // one launch
+  int kind;           // 0 synth, 1 analysis, 2 blur, 3 blur adjoint
+  int key0, key1;     // (L, bc) or (radius, 0)
+  int n = 0, total = 0;
+  size_t lds = 0;
+  std::vector<unsigned char> items;
+  std::vector<int> prefix;
+  size_t items_dev = 0, prefix_dev = 0;  // offsets in the device blob
+};
+
+struct Stage {
+  std::vector<Group> groups;
+};
+
+}  // namespace
+
+struct aw_batch {
+  int n = 0;
+  std::vector<Image> img;
+  std::vector<long long> coef_off, img_off;
+  int var[4] = {0, 0, 0, 4};
+  // workspace layout (bytes)
+  size_t grad_off = 0, rpart_off = 0, l1_off = 0, dx_off = 0, obj_off = 0, ctr_off = 0,
+         act_off = 0, beta_off = 0, ws_total = 0;
+  std::vector<int> r_off;   // per-image first residual-partial slot (n + 1)
+  std::vector<int> blk_off; // per-image first prox block (n + 1)
+  // bound state
+  bool bound = false;
+  const void* b_obs = nullptr;
+  void* x = nullptr;
+  void* y = nullptr;
+  char* ws = nullptr;
+  double lambda = 0, Lstep = 1;
+  std::vector<Stage> stages;
+  std::vector<aw::ProxItem> prox_items;
+  size_t prox_items_dev = 0, prox_prefix_dev = 0, rpref_dev = 0, bpref_dev = 0;
+  char* blob = nullptr;
+  hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+thread_local std::string b_err;
+aw_status bfail(aw_status st, const char* msg) {
+  b_err = msg;
+  return st;
+}
+
+// Tables and per-level sizes of one image (validation mirrors the single-image path).
+aw_status image_setup(const aw_wavelet& w, const aw_blur& b, Image& im) {
+  int64_t n = 0;
+  int32_t sr[AW_MAX_LEVELS + 1], sc[AW_MAX_LEVELS + 1];
+  aw_status st = aw_wavelet_layout(&w, &n, sr, sc);
+  if (st != AW_OK) return bfail(st, aw_last_error());
+  if (w.bc == AW_BC_PER_EXT) return bfail(AW_EUNSUPPORTED, "batched path: periodic extension not supported");
+  if (b.rows != w.rows || b.cols != w.cols) return bfail(AW_EINVAL, "wavelet and blur sizes differ");
+  if (b.radius < 0 || b.radius > AW_MAX_RADIUS) return bfail(AW_EINVAL, "radius out of range");
+  im.w = w;
+  im.J = w.levels;
+  im.L = w.filter_len;
+  im.bc = w.bc;
+  im.e = (w.bc == AW_BC_SYM) ? w.filter_len - 1 : 0;
+  im.rows = w.rows;
+  im.cols = w.cols;
+  for (int j = 0; j <= im.J; ++j) {
+    im.sr[j] = sr[j];
+    im.sc[j] = sc[j];
+    if (j < im.J && im.bc == AW_BC_SYM && (sr[j] < im.e || sc[j] < im.e))
+      return bfail(AW_EUNSUPPORTED, "batched path: level shorter than the extension width");
+  }
+  im.ncoef = n;
+  im.npix = (long long)w.rows * w.cols;
+  long long o = (long long)sr[im.J] * sc[im.J];
+  im.off_hvd[im.J] = o;
+  for (int j = im.J; j >= 1; --j) {
+    o += 3LL * sr[j] * sc[j];
+    if (j > 1) im.off_hvd[j - 1] = o;
+  }
+  im.b.rows = b.rows;
+  im.b.cols = b.cols;
+  im.b.radius = b.radius;
+  for (int i = 0; i < 2 * b.radius + 1; ++i) {
+    if (!std::isfinite(b.taps[i])) return bfail(AW_EINVAL, "PSF tap not finite");
+    im.b.taps[i] = b.taps[i];
+  }
+  return AW_OK;
+}
+
+void layout(aw_batch* p) {
+  size_t off = 0;
+  const size_t ts = sizeof(float);
+  p->coef_off.assign(p->n + 1, 0);
+  p->img_off.assign(p->n + 1, 0);
+  for (int i = 0; i < p->n; ++i) {
+    p->coef_off[i + 1] = p->coef_off[i] + p->img[i].ncoef;
+    p->img_off[i + 1] = p->img_off[i] + p->img[i].npix;
+  }
+  for (int i = 0; i < p->n; ++i) {
+    Image& im = p->img[i];
+    for (int j = 1; j < im.J; ++j) {
+      im.a_off[j] = off;
+      off = alignb(off + (size_t)im.sr[j] * im.sc[j] * ts);
+    }
+    im.tmp_off = off;
+    off = alignb(off + (size_t)im.npix * ts);
+    im.res_off = off;
+    off = alignb(off + (size_t)im.npix * ts);
+  }
+  p->grad_off = off;
+  off = alignb(off + (size_t)p->coef_off[p->n] * ts);
+  p->r_off.assign(p->n + 1, 0);
+  p->blk_off.assign(p->n + 1, 0);
+  for (int i = 0; i < p->n; ++i) {
+    int tx;
+    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
+    p->blk_off[i + 1] =
+        p->blk_off[i] + (int)((p->img[i].ncoef + aw::kBatchProxChunk - 1) / aw::kBatchProxChunk);
+  }
+  // partial slots sized for the larger blur variant so the layout does not
+  // depend on the tile configuration
+  int rmax = 0;
+  for (int i = 0; i < p->n; ++i) {
+    int tx;
+    rmax += std::max(aw::blur_tiles_var(0, 0, p->img[i].b, &tx), aw::blur_tiles_var(0, 1, p->img[i].b, &tx));
+  }
+  p->rpart_off = off;
+  off = alignb(off + (size_t)rmax * sizeof(double));
+  p->l1_off = off;
+  off = alignb(off + (size_t)p->blk_off[p->n] * sizeof(double));
+  p->dx_off = off;
+  off = alignb(off + (size_t)p->blk_off[p->n] * sizeof(double));
+  p->obj_off = off;
+  off = alignb(off + (size_t)p->n * 3 * sizeof(double));
+  p->ctr_off = off;
+  off = alignb(off + sizeof(int));
+  p->act_off = off;
+  off = alignb(off + (size_t)p->n * sizeof(int));
+  p->beta_off = off;
+  off = alignb(off + (size_t)kBetaLen * sizeof(double));
+  p->ws_total = off;
+}
+
+Group& group_for(Stage& st, int kind, int k0, int k1) {
+  for (Group& g : st.groups)
+    if (g.kind == kind && g.key0 == k0 && g.key1 == k1) return g;
+  st.groups.push_back(Group{});
+  Group& g = st.groups.back();
+  g.kind = kind;
+  g.key0 = k0;
+  g.key1 = k1;
+  g.prefix.push_back(0);
+  return g;
+}
+
+void add_item(Group& g, const void* item, size_t sz, int tiles) {
+  const unsigned char* c = static_cast<const unsigned char*>(item);
+  g.items.insert(g.items.end(), c, c + sz);
+  g.n += 1;
+  g.total += tiles;
+  g.prefix.push_back(g.total);
+}
+
+aw_status build(aw_batch* p) {
+  p->stages.clear();
+  int Jmax = 0;
+  for (const Image& im : p->img) Jmax = std::max(Jmax, im.J);
+  char* ws = p->ws;
+  float* grad = reinterpret_cast<float*>(ws + p->grad_off);
+  double* rpart = reinterpret_cast<double*>(ws + p->rpart_off);
+  // recompute residual-partial offsets for the current blur variant
+  for (int i = 0; i < p->n; ++i) {
+    int tx;
+    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
+  }
+  std::vector<unsigned char> buf(std::max({aw::synth_item_size(0), aw::ana_item_size(0),
+                                           aw::blur_item_size(0)}));
+  // synthesis levels Jmax .. 1
+  for (int j = Jmax; j >= 1; --j) {
+    Stage st;
+    for (int i = 0; i < p->n; ++i) {
+      const Image& im = p->img[i];
+      if (im.J < j) continue;
+      const float* yi = static_cast<const float*>(p->y) + p->coef_off[i];
+      aw::SynthLevel d{};
+      d.a = (j == im.J) ? (const void*)yi : (const void*)(ws + im.a_off[j]);
+      d.stride_a = 0;
+      d.hvd = yi + im.off_hvd[j];
+      d.stride_hvd = 0;
+      d.out = (j == 1) ? (void*)(ws + im.tmp_off) : (void*)(ws + im.a_off[j - 1]);
+      d.stride_out = 0;
+      d.r = {im.sr[j - 1], im.sr[j], im.e};
+      d.c = {im.sc[j - 1], im.sc[j], im.e};
+      d.bc = im.bc;
+      d.pinv = 1;
+      aw::make_synth_item(0, d, im.w.lo, im.L, i, buf.data());
+      Group& g = group_for(st, 0, im.L, im.bc);
+      add_item(g, buf.data(), aw::synth_item_size(0), aw::synth_tiles(0, p->var[0], d));
+      g.lds = std::max(g.lds, aw::synth_item_lds(0, im.L, p->var[0], d));
+      if (g.lds > 160 * 1024) return bfail(AW_EUNSUPPORTED, "tile window exceeds LDS");
+    }
+    p->stages.push_back(std::move(st));
+  }
+  // R y - b and R^* r
+  for (int adj = 0; adj < 2; ++adj) {
+    Stage st;
+    for (int i = 0; i < p->n; ++i) {
+      const Image& im = p->img[i];
+      int tx;
+      const int tiles = aw::blur_tiles_var(0, p->var[2], im.b, &tx);
+      const float* bi = static_cast<const float*>(p->b_obs) + p->img_off[i];
+      if (!adj)
+        aw::make_blur_item(0, false, im.b, ws + im.tmp_off, ws + im.res_off, bi, rpart + p->r_off[i],
+                           i, tx, buf.data());
+      else
+        aw::make_blur_item(0, true, im.b, ws + im.res_off, ws + im.tmp_off, nullptr, nullptr, i, tx,
+                           buf.data());
+      Group& g = group_for(st, 2 + adj, im.b.radius, 0);
+      add_item(g, buf.data(), aw::blur_item_size(0), tiles);
+    }
+    p->stages.push_back(std::move(st));
+  }
+  // analysis levels 1 .. Jmax (W^*: weights 1/mult)
+  for (int j = 1; j <= Jmax; ++j) {
+    Stage st;
+    for (int i = 0; i < p->n; ++i) {
+      const Image& im = p->img[i];
+      if (im.J < j) continue;
+      float* gi = grad + p->coef_off[i];
+      aw::AnaLevel d{};
+      d.in = (j == 1) ? (const void*)(ws + im.tmp_off) : (const void*)(ws + im.a_off[j - 1]);
+      d.stride_in = 0;
+      d.a = (j == im.J) ? (void*)gi : (void*)(ws + im.a_off[j]);
+      d.stride_a = 0;
+      d.hvd = gi + im.off_hvd[j];
+      d.stride_hvd = 0;
+      d.r = {im.sr[j - 1], im.sr[j], im.e};
+      d.c = {im.sc[j - 1], im.sc[j], im.e};
+      d.bc = im.bc;
+      d.pinv = 1;
+      aw::make_ana_item(0, d, im.w.lo, im.L, i, buf.data());
+      Group& g = group_for(st, 1, im.L, im.bc);
+      add_item(g, buf.data(), aw::ana_item_size(0), aw::ana_tiles(0, p->var[1], d));
+    }
+    p->stages.push_back(std::move(st));
+  }
+  // device blob: all groups' items and prefixes, prox items and prefixes
+  p->prox_items.clear();
+  std::vector<int> prox_prefix(1, 0);
+  for (int i = 0; i < p->n; ++i) {
+    p->prox_items.push_back(aw::ProxItem{p->coef_off[i], p->img[i].ncoef, i});
+    prox_prefix.push_back(p->blk_off[i + 1]);
+  }
+  size_t off = 0;
+  for (Stage& st : p->stages)
+    for (Group& g : st.groups) {
+      g.items_dev = off;
+      off = alignb(off + g.items.size());
+      g.prefix_dev = off;
+      off = alignb(off + g.prefix.size() * sizeof(int));
+    }
+  p->prox_items_dev = off;
+  off = alignb(off + p->prox_items.size() * sizeof(aw::ProxItem));
+  p->prox_prefix_dev = off;
+  off = alignb(off + prox_prefix.size() * sizeof(int));
+  p->rpref_dev = off;
+  off = alignb(off + p->r_off.size() * sizeof(int));
+  p->bpref_dev = off;
+  off = alignb(off + p->blk_off.size() * sizeof(int));
+  if (p->blob) hipFree(p->blob);
+  p->blob = nullptr;
+  if (hipMalloc((void**)&p->blob, off) != hipSuccess) return bfail(AW_EHIP, "plan allocation failed");
+  std::vector<unsigned char> host(off, 0);
+  for (Stage& st : p->stages)
+    for (Group& g : st.groups) {
+      std::copy(g.items.begin(), g.items.end(), host.begin() + g.items_dev);
+      std::memcpy(host.data() + g.prefix_dev, g.prefix.data(), g.prefix.size() * sizeof(int));
+    }
+  std::memcpy(host.data() + p->prox_items_dev, p->prox_items.data(),
+              p->prox_items.size() * sizeof(aw::ProxItem));
+  std::memcpy(host.data() + p->prox_prefix_dev, prox_prefix.data(), prox_prefix.size() * sizeof(int));
+  std::memcpy(host.data() + p->rpref_dev, p->r_off.data(), p->r_off.size() * sizeof(int));
+  std::memcpy(host.data() + p->bpref_dev, p->blk_off.data(), p->blk_off.size() * sizeof(int));
+  if (hipMemcpy(p->blob, host.data(), off, hipMemcpyHostToDevice) != hipSuccess)
+    return bfail(AW_EHIP, "plan upload failed");
+  // events for fork / join
+  size_t need = 0;
+  for (const Stage& st : p->stages) need += st.groups.size() + 1;
+  while (p->events.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return bfail(AW_EHIP, "event creation failed");
+    p->events.push_back(e);
+  }
+  return AW_OK;
+}
+
+aw_status launch_group(aw_batch* p, const Group& g, hipStream_t s) {
+  const int* active = reinterpret_cast<const int*>(p->ws + p->act_off);
+  const void* items = p->blob + g.items_dev;
+  const int* prefix = reinterpret_cast<const int*>(p->blob + g.prefix_dev);
+  hipError_t e = hipSuccess;
+  if (g.total == 0) return AW_OK;
+  switch (g.kind) {
+    case 0:
+      e = aw::launch_synth_batch(0, g.key0, g.key1, p->var[0], items, prefix, g.n, g.total, active,
+                                 g.lds, s);
+      break;
+    case 1:
+      e = aw::launch_ana_batch(0, g.key0, g.key1, p->var[1], items, prefix, g.n, g.total, active, s);
+      break;
+    default:
+      e = aw::launch_blur_batch(0, g.key0, g.kind == 3, p->var[2], items, prefix, g.n, g.total,
+                                active, s);
+  }
+  if (e != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(e));
+  return AW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+aw_status aw_batch_create(int32_t n, const aw_wavelet* w, const aw_blur* b, aw_batch** plan) {
+  if (!plan || !w || !b || n < 1) return bfail(AW_EINVAL, "invalid plan arguments");
+  *plan = nullptr;
+  aw_batch* p = new aw_batch();
+  p->n = n;
+  p->img.resize(n);
+  for (int i = 0; i < n; ++i) {
+    aw_status st = image_setup(w[i], b[i], p->img[i]);
+    if (st != AW_OK) {
+      delete p;
+      return st;
+    }
+  }
+  layout(p);
+  for (int k = 0; k < 4; ++k)
+    if (hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking) != hipSuccess) {
+      delete p;
+      return bfail(AW_EHIP, "stream creation failed");
+    }
+  *plan = p;
+  b_err.clear();
+  return AW_OK;
+}
+
+aw_status aw_batch_destroy(aw_batch* p) {
+  if (!p) return AW_OK;
+  if (p->blob) hipFree(p->blob);
+  for (hipEvent_t e : p->events) hipEventDestroy(e);
+  for (int k = 0; k < 4; ++k)
+    if (p->aux[k]) hipStreamDestroy(p->aux[k]);
+  delete p;
+  return AW_OK;
+}
+
+aw_status aw_batch_layout(const aw_batch* p, int64_t* coef_off, int64_t* img_off,
+                          size_t* workspace_bytes) {
+  if (!p) return bfail(AW_EINVAL, "plan is NULL");
+  for (int i = 0; i <= p->n; ++i) {
+    if (coef_off) coef_off[i] = p->coef_off[i];
+    if (img_off) img_off[i] = p->img_off[i];
+  }
+  if (workspace_bytes) *workspace_bytes = p->ws_total;
+  return AW_OK;
+}
+
+aw_status aw_batch_set_config(aw_batch* p, const int32_t* var) {
+  if (!p || !var) return bfail(AW_EINVAL, "invalid arguments");
+  for (int k = 0; k < 3; ++k)
+    if (var[k] != 0 && var[k] != 1) return bfail(AW_EINVAL, "tile variant must be 0 or 1");
+  if (var[3] < 1 || var[3] > 4) return bfail(AW_EINVAL, "streams must be 1..4");
+  for (int k = 0; k < 4; ++k) p->var[k] = var[k];
+  if (p->bound) return build(p);
+  return AW_OK;
+}
+
+aw_status aw_batch_bind(aw_batch* p, const void* b_obs, void* x, void* y, void* workspace,
+                        size_t workspace_bytes, double lambda, double L) {
+  if (!p || !b_obs || !x || !y || !workspace) return bfail(AW_EINVAL, "NULL argument");
+  if (workspace_bytes < p->ws_total) return bfail(AW_EINVAL, "workspace too small");
+  if (!(L > 0.0) || !(lambda >= 0.0)) return bfail(AW_EINVAL, "L > 0 and lambda >= 0 required");
+  p->b_obs = b_obs;
+  p->x = x;
+  p->y = y;
+  p->ws = static_cast<char*>(workspace);
+  p->lambda = lambda;
+  p->Lstep = L;
+  // beta_k = (t_k - 1) / t_{k+1}, t_1 = 1
+  std::vector<double> beta(kBetaLen);
+  double t = 1.0;
+  for (int k = 0; k < kBetaLen; ++k) {
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    beta[k] = (t - 1.0) / tn;
+    t = tn;
+  }
+  if (hipMemcpy(p->ws + p->beta_off, beta.data(), kBetaLen * sizeof(double),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return bfail(AW_EHIP, "beta table upload failed");
+  p->bound = true;
+  aw_status st = build(p);
+  if (st == AW_OK) b_err.clear();
+  return st;
+}
+
+aw_status aw_batch_control(const aw_batch* p, int32_t** counter, int32_t** active, double** obj) {
+  if (!p || !p->bound) return bfail(AW_EINVAL, "plan not bound");
+  if (counter) *counter = reinterpret_cast<int32_t*>(p->ws + p->ctr_off);
+  if (active) *active = reinterpret_cast<int32_t*>(p->ws + p->act_off);
+  if (obj) *obj = reinterpret_cast<double*>(p->ws + p->obj_off);
+  return AW_OK;
+}
+
+aw_status aw_batch_reset(aw_batch* p, void* stream) {
+  if (!p || !p->bound) return bfail(AW_EINVAL, "plan not bound");
+  const long long nc = p->coef_off[p->n];
+  hipLaunchKernelGGL(aw::batch_reset_kernel<float>, dim3(1024), dim3(256), 0, (hipStream_t)stream,
+                     reinterpret_cast<int*>(p->ws + p->ctr_off),
+                     reinterpret_cast<int*>(p->ws + p->act_off), p->n, static_cast<float*>(p->x),
+                     static_cast<float*>(p->y), nc);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AW_OK : bfail(AW_EHIP, hipGetErrorString(e));
+}
+
+aw_status aw_batch_step(aw_batch* p, void* stream) {
+  if (!p || !p->bound) return bfail(AW_EINVAL, "plan not bound");
+  hipStream_t s = (hipStream_t)stream;
+  size_t ev = 0;
+  for (const Stage& st : p->stages) {
+    const int ng = (int)st.groups.size();
+    if (ng <= 1 || p->var[3] <= 1) {
+      for (const Group& g : st.groups) {
+        aw_status r = launch_group(p, g, s);
+        if (r != AW_OK) return r;
+      }
+      continue;
+    }
+    // fork the classes of this stage over auxiliary streams, then join
+    hipEvent_t fork = p->events[ev++];
+    if (hipEventRecord(fork, s) != hipSuccess) return bfail(AW_EHIP, "event record failed");
+    for (int gi = 0; gi < ng; ++gi) {
+      hipStream_t a = p->aux[gi % p->var[3]];
+      if (hipStreamWaitEvent(a, fork, 0) != hipSuccess) return bfail(AW_EHIP, "stream wait failed");
+      aw_status r = launch_group(p, st.groups[gi], a);
+      if (r != AW_OK) return r;
+      hipEvent_t done = p->events[ev++];
+      if (hipEventRecord(done, a) != hipSuccess) return bfail(AW_EHIP, "event record failed");
+      if (hipStreamWaitEvent(s, done, 0) != hipSuccess) return bfail(AW_EHIP, "stream wait failed");
+    }
+  }
+  char* ws = p->ws;
+  const int total_blocks = p->blk_off[p->n];
+  hipError_t e = aw::launch_batch_prox(
+      reinterpret_cast<const aw::ProxItem*>(p->blob + p->prox_items_dev),
+      reinterpret_cast<const int*>(p->blob + p->prox_prefix_dev), p->n, total_blocks,
+      reinterpret_cast<const int*>(ws + p->act_off), reinterpret_cast<const float*>(ws + p->grad_off),
+      static_cast<float*>(p->x), static_cast<float*>(p->y), 1.0 / p->Lstep, p->lambda / p->Lstep,
+      reinterpret_cast<const double*>(ws + p->beta_off), kBetaLen,
+      reinterpret_cast<const int*>(ws + p->ctr_off), reinterpret_cast<double*>(ws + p->l1_off),
+      reinterpret_cast<double*>(ws + p->dx_off), s);
+  if (e != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(e));
+  hipLaunchKernelGGL(aw::batch_reduce_kernel, dim3(p->n), dim3(256), 0, s, p->n,
+                     reinterpret_cast<const int*>(p->blob + p->rpref_dev),
+                     reinterpret_cast<const double*>(ws + p->rpart_off),
+                     reinterpret_cast<const int*>(p->blob + p->bpref_dev),
+                     reinterpret_cast<const double*>(ws + p->l1_off),
+                     reinterpret_cast<const double*>(ws + p->dx_off),
+                     reinterpret_cast<const int*>(ws + p->act_off),
+                     reinterpret_cast<double*>(ws + p->obj_off));
+  hipLaunchKernelGGL(aw::batch_counter_kernel, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<int*>(ws + p->ctr_off));
+  e = hipGetLastError();
+  return e == hipSuccess ? AW_OK : bfail(AW_EHIP, hipGetErrorString(e));
+}
+
+const char* aw_batch_last_error(void) { return b_err.c_str(); }
+
+}  // extern "C"

@@ -25,24 +25,18 @@
 
 namespace aw {
 
-template <typename T>
+// Tile shapes; variant 1 halves the rows. NT = 512 threads.
+template <typename T, int VAR = 0>
 struct BlurCfg;
-template <>
-struct BlurCfg<float> {
-  static constexpr int TR = 64, TC = 64, VW = 4, NT = 512;
+template <int VAR>
+struct BlurCfg<float, VAR> {
+  static constexpr int TR = 64 >> VAR, TC = 64, VW = 4, NT = 512;
   using V = float4;
 };
-template <>
-struct BlurCfg<double> {
-  static constexpr int TR = 32, TC = 32, VW = 2, NT = 512;
+template <int VAR>
+struct BlurCfg<double, VAR> {
+  static constexpr int TR = 32 >> VAR, TC = 32, VW = 2, NT = 512;
   using V = double2;
-};
-
-template <typename T>
-struct BlurArgs {
-  int rows, cols;
-  int symmetric;               // taps symmetric: the R^* border correction vanishes
-  T taps[2 * kMaxRadius + 1];  // correlation order: out[p] = sum_k t[k] in[p - r + k]
 };
 
 __device__ inline int refl_idx(int m, int N) {
@@ -58,12 +52,11 @@ __device__ inline bool refl_odd(int m, int N) {
   return (floordiv(m, N) & 1) != 0;
 }
 
-template <typename T, int R, bool ADJ>
-__global__ __launch_bounds__(BlurCfg<T>::NT) void blur_tile_kernel(BlurArgs<T> a, const T* __restrict__ X,
-                                                        T* __restrict__ Y,
-                                                        const T* __restrict__ SUB,
-                                                        double* __restrict__ partials) {
-  using Cfg = BlurCfg<T>;
+template <typename T, int R, bool ADJ, int VAR>
+__device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restrict__ X,
+                                          T* __restrict__ Y, const T* __restrict__ SUB,
+                                          double* __restrict__ part_out, int bx, int by, int img) {
+  using Cfg = BlurCfg<T, VAR>;
   using V = typename Cfg::V;
   constexpr int TR = Cfg::TR, TC = Cfg::TC, VW = Cfg::VW, NT = Cfg::NT;
   constexpr int WR = TR + 2 * R;                       // window rows
@@ -77,8 +70,7 @@ __global__ __launch_bounds__(BlurCfg<T>::NT) void blur_tile_kernel(BlurArgs<T> a
   __shared__ double red[NT];
 
   const int N = a.rows, M = a.cols;
-  const int img = blockIdx.z;
-  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * TC;
+  const int r0 = by * TR, c0 = bx * TC;
   const long long plane = (long long)N * M;
   const T* Xi = X + img * plane;
   T t[K];
@@ -222,23 +214,46 @@ __global__ __launch_bounds__(BlurCfg<T>::NT) void blur_tile_kernel(BlurArgs<T> a
       }
     }
   }
-  if (partials) {
+  if (part_out) {
     red[threadIdx.x] = part;
     __syncthreads();
     for (int s = NT / 2; s > 0; s >>= 1) {
       if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
       __syncthreads();
     }
-    if (threadIdx.x == 0)
-      partials[(long long)img * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
-          red[0];
+    if (threadIdx.x == 0) *part_out = red[0];
   }
 }
 
-template <typename T>
+template <typename T, int R, bool ADJ, int VAR>
+__global__ __launch_bounds__(512) void blur_tile_kernel(BlurArgs<T> a, const T* __restrict__ X,
+                                                        T* __restrict__ Y,
+                                                        const T* __restrict__ SUB,
+                                                        double* __restrict__ partials) {
+  double* po = partials ? partials + (long long)blockIdx.z * gridDim.x * gridDim.y +
+                              blockIdx.y * gridDim.x + blockIdx.x
+                        : nullptr;
+  blur_tile<T, R, ADJ, VAR>(a, X, Y, SUB, po, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// One launch over tiles of several images: items[i] covers tiles
+// [prefix[i], prefix[i+1]); partials (if any) go to the image's tile slots.
+template <typename T, int R, bool ADJ, int VAR>
+__global__ __launch_bounds__(512) void blur_batch_kernel(const BlurItem<T>* __restrict__ items,
+                                                         const int* __restrict__ prefix, int n,
+                                                         const int* __restrict__ active) {
+  const int i = find_item(prefix, n, blockIdx.x);
+  const BlurItem<T>& it = items[i];
+  if (active && !active[it.image]) return;
+  const int t = blockIdx.x - prefix[i];
+  double* po = it.partials ? it.partials + t : nullptr;
+  blur_tile<T, R, ADJ, VAR>(it.a, it.x, it.y, it.sub, po, t % it.tiles_x, t / it.tiles_x, 0);
+}
+
+template <typename T, int VAR = 0>
 static dim3 blur_grid(const BlurDesc& b, int batch) {
-  return dim3((b.cols + BlurCfg<T>::TC - 1) / BlurCfg<T>::TC,
-              (b.rows + BlurCfg<T>::TR - 1) / BlurCfg<T>::TR, batch);
+  return dim3((b.cols + BlurCfg<T, VAR>::TC - 1) / BlurCfg<T, VAR>::TC,
+              (b.rows + BlurCfg<T, VAR>::TR - 1) / BlurCfg<T, VAR>::TR, batch);
 }
 
 int blur_tiles(int dtype, const BlurDesc& b) {
@@ -247,7 +262,7 @@ int blur_tiles(int dtype, const BlurDesc& b) {
 }
 
 template <typename T, bool ADJ>
-static BlurArgs<T> make_args(const BlurDesc& b) {
+BlurArgs<T> make_blur_args(const BlurDesc& b) {
   BlurArgs<T> a{};
   a.rows = b.rows;
   a.cols = b.cols;
@@ -263,8 +278,8 @@ static BlurArgs<T> make_args(const BlurDesc& b) {
 template <typename T, int R, bool ADJ>
 static hipError_t launch_r(const BlurDesc& b, int batch, const void* x, void* y, const void* sub,
                            double* partials, hipStream_t s) {
-  hipLaunchKernelGGL((blur_tile_kernel<T, R, ADJ>), blur_grid<T>(b, batch), dim3(BlurCfg<T>::NT), 0, s,
-                     make_args<T, ADJ>(b), static_cast<const T*>(x), static_cast<T*>(y),
+  hipLaunchKernelGGL((blur_tile_kernel<T, R, ADJ, 0>), blur_grid<T>(b, batch), dim3(512), 0, s,
+                     make_blur_args<T, ADJ>(b), static_cast<const T*>(x), static_cast<T*>(y),
                      static_cast<const T*>(sub), partials);
   return hipGetLastError();
 }
@@ -280,6 +295,65 @@ static hipError_t launch_t(const BlurDesc& b, int batch, const void* x, void* y,
 #undef AW_R
     default: return hipErrorInvalidValue;
   }
+}
+
+int blur_tiles_var(int dtype, int var, const BlurDesc& b, int* tiles_x) {
+  dim3 g;
+  if (dtype)
+    g = var ? blur_grid<double, 1>(b, 1) : blur_grid<double, 0>(b, 1);
+  else
+    g = var ? blur_grid<float, 1>(b, 1) : blur_grid<float, 0>(b, 1);
+  if (tiles_x) *tiles_x = (int)g.x;
+  return (int)(g.x * g.y);
+}
+
+size_t blur_item_size(int dtype) { return dtype ? sizeof(BlurItem<double>) : sizeof(BlurItem<float>); }
+
+void make_blur_item(int dtype, bool adj, const BlurDesc& b, const void* x, void* y, const void* sub,
+                    double* partials, int image, int tiles_x, void* out) {
+  if (dtype) {
+    BlurItem<double> it{adj ? make_blur_args<double, true>(b) : make_blur_args<double, false>(b),
+                        static_cast<const double*>(x), static_cast<double*>(y),
+                        static_cast<const double*>(sub), partials, image, tiles_x};
+    *static_cast<BlurItem<double>*>(out) = it;
+  } else {
+    BlurItem<float> it{adj ? make_blur_args<float, true>(b) : make_blur_args<float, false>(b),
+                       static_cast<const float*>(x), static_cast<float*>(y),
+                       static_cast<const float*>(sub), partials, image, tiles_x};
+    *static_cast<BlurItem<float>*>(out) = it;
+  }
+}
+
+template <typename T, int R, bool ADJ, int VAR>
+static hipError_t launch_blur_batch_r(const void* items, const int* prefix, int n, int total,
+                                      const int* active, hipStream_t s) {
+  hipLaunchKernelGGL((blur_batch_kernel<T, R, ADJ, VAR>), dim3(total), dim3(512), 0, s,
+                     static_cast<const BlurItem<T>*>(items), prefix, n, active);
+  return hipGetLastError();
+}
+
+template <typename T, bool ADJ, int VAR>
+static hipError_t launch_blur_batch_t(int radius, const void* items, const int* prefix, int n,
+                                      int total, const int* active, hipStream_t s) {
+  switch (radius) {
+#define AW_R(r) \
+  case r: return launch_blur_batch_r<T, r, ADJ, VAR>(items, prefix, n, total, active, s);
+    AW_R(0) AW_R(1) AW_R(2) AW_R(3) AW_R(4) AW_R(5) AW_R(6) AW_R(7) AW_R(8) AW_R(9) AW_R(10)
+    AW_R(11) AW_R(12)
+#undef AW_R
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_blur_batch(int dtype, int radius, bool adj, int var, const void* items,
+                             const int* prefix, int n, int total, const int* active,
+                             hipStream_t s) {
+  if (dtype) return hipErrorInvalidValue;  // batched path: FP32
+  if (adj)
+    return var ? launch_blur_batch_t<float, true, 1>(radius, items, prefix, n, total, active, s)
+               : launch_blur_batch_t<float, true, 0>(radius, items, prefix, n, total, active, s);
+  return var ? launch_blur_batch_t<float, false, 1>(radius, items, prefix, n, total, active, s)
+             : launch_blur_batch_t<float, false, 0>(radius, items, prefix, n, total, active, s);
 }
 
 hipError_t launch_blur(int dtype, const BlurDesc& b, int batch, const void* x, void* y,

@@ -19,25 +19,15 @@
 
 namespace aw {
 
-template <typename T>
-struct SynthTile;
-template <>
-struct SynthTile<float> {
-  static constexpr int TR = 32, TC = 64;
+// Tile shapes; variant 1 halves the rows (more, smaller tiles for small
+// levels). The batched path picks the variant per launch (autotuned).
+template <typename T, int V = 0>
+struct SynthTile {
+  static constexpr int TR = (sizeof(T) == 4 ? 32 : 16) >> V, TC = 64;
 };
-template <>
-struct SynthTile<double> {
-  static constexpr int TR = 16, TC = 64;
-};
-template <typename T>
-struct AnaTile;
-template <>
-struct AnaTile<float> {
-  static constexpr int TKR = 32, TKC = 32, NT = 512;
-};
-template <>
-struct AnaTile<double> {
-  static constexpr int TKR = 16, TKC = 32, NT = 512;
+template <typename T, int V = 0>
+struct AnaTile {
+  static constexpr int TKR = (sizeof(T) == 4 ? 32 : 16) >> V, TKC = 32, NT = 512;
 };
 
 template <typename T>
@@ -120,23 +110,22 @@ __device__ inline int special_pos(int t, int sL, int sR) {
   return t < 2 * sL ? t : 2 * sR + (t - 2 * sL);
 }
 
-template <typename T, int L, int BC>
-__global__ __launch_bounds__(512) void synth_level_kernel(SynthLevel d, Taps<T> f) {
-  constexpr int TR = SynthTile<T>::TR, TC = SynthTile<T>::TC;
+template <typename T, int L, int BC, int V>
+__device__ __forceinline__ void synth_tile(const SynthLevel& d, const Taps<T>& f, int bx, int by,
+                                           int img, unsigned char* smem_raw) {
+  constexpr int TR = SynthTile<T, V>::TR, TC = SynthTile<T, V>::TC;
   constexpr int HL = L / 2;
   // extended modes shift the signal by e = L - 1 (odd): the first row of a
   // pair has odd n and the second row uses the next coefficient row
   constexpr bool SHIFT = (BC == SYM);
   using V2 = typename Vec<T>::V2;
   using V4 = typename Vec<T>::V4;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
 
-  const int img = blockIdx.z;
   const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
   const int er = SHIFT ? d.r.e : 0;
   const int ec = SHIFT ? d.c.e : 0;
-  const int r0 = blockIdx.y * TR, r1 = min(r0 + TR, Nr);
-  const int c0 = blockIdx.x * TC, c1 = min(c0 + TC, Nc);
+  const int r0 = by * TR, r1 = min(r0 + TR, Nr);
+  const int c0 = bx * TC, c1 = min(c0 + TC, Nc);
   int nlo_r, nhi_r, nlo_c, nhi_c;
   fold_window(r0, r1, Nr, er, nlo_r, nhi_r);
   fold_window(c0, c1, Nc, ec, nlo_c, nhi_c);
@@ -327,6 +316,27 @@ __global__ __launch_bounds__(512) void synth_level_kernel(SynthLevel d, Taps<T> 
   }
 }
 
+template <typename T, int L, int BC, int V>
+__global__ __launch_bounds__(512) void synth_level_kernel(SynthLevel d, Taps<T> f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  synth_tile<T, L, BC, V>(d, f, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+}
+
+// One launch over tiles of several images (a tile queue): items[i] covers
+// tiles [prefix[i], prefix[i+1]) of its image; inactive images return.
+template <typename T, int L, int BC, int V>
+__global__ __launch_bounds__(512) void synth_batch_kernel(const SynthItem<T>* __restrict__ items,
+                                                          const int* __restrict__ prefix, int n,
+                                                          const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = find_item(prefix, n, blockIdx.x);
+  const SynthItem<T>& it = items[i];
+  if (active && !active[it.image]) return;
+  const int t = blockIdx.x - prefix[i];
+  const int tx = (it.d.c.N + SynthTile<T, V>::TC - 1) / SynthTile<T, V>::TC;
+  synth_tile<T, L, BC, V>(it.d, it.f, t % tx, t / tx, 0, smem_raw);
+}
+
 static int synth_max_window(const Axis& a, int L, int bc, int tile) {
   const int e = (bc == SYM) ? a.e : 0;
   int mx = 0;
@@ -340,11 +350,11 @@ static int synth_max_window(const Axis& a, int L, int bc, int tile) {
   return mx;
 }
 
-template <typename T>
+template <typename T, int V = 0>
 static size_t synth_lds_t(int L, const SynthLevel& d) {
-  const int mr = synth_max_window(d.r, L, d.bc, SynthTile<T>::TR);
-  const int mc = synth_max_window(d.c, L, d.bc, SynthTile<T>::TC);
-  return sizeof(T) * (size_t)(4 * mr * mc + 2 * SynthTile<T>::TR * mc);
+  const int mr = synth_max_window(d.r, L, d.bc, SynthTile<T, V>::TR);
+  const int mc = synth_max_window(d.c, L, d.bc, SynthTile<T, V>::TC);
+  return sizeof(T) * (size_t)(4 * mr * mc + 2 * SynthTile<T, V>::TR * mc);
 }
 
 size_t synth_level_lds(int dtype, int L, const SynthLevel& d) {
@@ -354,7 +364,7 @@ size_t synth_level_lds(int dtype, int L, const SynthLevel& d) {
 template <typename T, int L, int BC>
 static hipError_t launch_synth_t(const double* lo, const SynthLevel& d, int batch, hipStream_t s) {
   const size_t lds = synth_lds_t<T>(L, d);
-  auto kern = synth_level_kernel<T, L, BC>;
+  auto kern = synth_level_kernel<T, L, BC, 0>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -394,9 +404,10 @@ hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLev
 }
 
 // ----------------------------------------------------------------- analysis
-template <typename T, int L, int BC>
-__global__ __launch_bounds__(AnaTile<T>::NT) void ana_level_kernel(AnaLevel d, Taps<T> f) {
-  constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC, NT = AnaTile<T>::NT;
+template <typename T, int L, int BC, int VAR>
+__device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, int bx, int by,
+                                         int img) {
+  constexpr int TKR = AnaTile<T, VAR>::TKR, TKC = AnaTile<T, VAR>::TKC, NT = AnaTile<T, VAR>::NT;
   constexpr int NWR = 2 * TKR + L - 2, NWC = 2 * TKC + L - 2;
   constexpr int VW = 16 / sizeof(T);                       // elements per 16-byte LDS read
   constexpr int SUS = ((NWC + VW - 1) / VW) * VW + VW;     // input row stride
@@ -406,11 +417,10 @@ __global__ __launch_bounds__(AnaTile<T>::NT) void ana_level_kernel(AnaLevel d, T
   __shared__ __align__(16) T su[NWR * SUS];
   __shared__ __align__(16) V2 slh[NWR * TKC];
 
-  const int img = blockIdx.z;
   const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
   const int er = d.r.e, ec = d.c.e;
-  const int kr0 = blockIdx.y * TKR, kr1 = min(kr0 + TKR, Kr);
-  const int kc0 = blockIdx.x * TKC, kc1 = min(kc0 + TKC, Kc);
+  const int kr0 = by * TKR, kr1 = min(kr0 + TKR, Kr);
+  const int kc0 = bx * TKC, kc1 = min(kc0 + TKC, Kc);
   const int nlo_r = (BC == PER) ? 2 * kr0 : 2 * kr0 - L + 2;
   const int nlo_c = (BC == PER) ? 2 * kc0 : 2 * kc0 - L + 2;
   const int Mr = Nr + 2 * er, Mc = Nc + 2 * ec;
@@ -579,11 +589,28 @@ __global__ __launch_bounds__(AnaTile<T>::NT) void ana_level_kernel(AnaLevel d, T
   }
 }
 
+template <typename T, int L, int BC, int VAR>
+__global__ __launch_bounds__(512) void ana_level_kernel(AnaLevel d, Taps<T> f) {
+  ana_tile<T, L, BC, VAR>(d, f, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, int L, int BC, int VAR>
+__global__ __launch_bounds__(512) void ana_batch_kernel(
+    const AnaItem<T>* __restrict__ items, const int* __restrict__ prefix, int n,
+    const int* __restrict__ active) {
+  const int i = find_item(prefix, n, blockIdx.x);
+  const AnaItem<T>& it = items[i];
+  if (active && !active[it.image]) return;
+  const int t = blockIdx.x - prefix[i];
+  const int tx = (it.d.c.K + AnaTile<T, VAR>::TKC - 1) / AnaTile<T, VAR>::TKC;
+  ana_tile<T, L, BC, VAR>(it.d, it.f, t % tx, t / tx, 0);
+}
+
 template <typename T, int L, int BC>
 static hipError_t launch_ana_t(const double* lo, const AnaLevel& d, int batch, hipStream_t s) {
   constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC;
   dim3 grid((d.c.K + TKC - 1) / TKC, (d.r.K + TKR - 1) / TKR, batch);
-  hipLaunchKernelGGL((ana_level_kernel<T, L, BC>), grid, dim3(AnaTile<T>::NT), 0, s, d,
+  hipLaunchKernelGGL((ana_level_kernel<T, L, BC, 0>), grid, dim3(AnaTile<T>::NT), 0, s, d,
                      make_taps<T>(lo, L));
   return hipGetLastError();
 }
@@ -614,6 +641,111 @@ hipError_t launch_ana_level(int dtype, int L, const double* lo, const AnaLevel& 
                             hipStream_t s) {
   return dtype ? launch_ana_L<double>(L, lo, d, batch, s) : launch_ana_L<float>(L, lo, d, batch, s);
 }
+
+// ------------------------------------------------------- batched launchers
+template <typename T, int V>
+static int synth_tiles_t(const SynthLevel& d) {
+  return ((d.c.N + SynthTile<T, V>::TC - 1) / SynthTile<T, V>::TC) *
+         ((d.r.N + SynthTile<T, V>::TR - 1) / SynthTile<T, V>::TR);
+}
+template <typename T, int V>
+static int ana_tiles_t(const AnaLevel& d) {
+  return ((d.c.K + AnaTile<T, V>::TKC - 1) / AnaTile<T, V>::TKC) *
+         ((d.r.K + AnaTile<T, V>::TKR - 1) / AnaTile<T, V>::TKR);
+}
+
+int synth_tiles(int dtype, int var, const SynthLevel& d) {
+  if (dtype) return var ? synth_tiles_t<double, 1>(d) : synth_tiles_t<double, 0>(d);
+  return var ? synth_tiles_t<float, 1>(d) : synth_tiles_t<float, 0>(d);
+}
+int ana_tiles(int dtype, int var, const AnaLevel& d) {
+  if (dtype) return var ? ana_tiles_t<double, 1>(d) : ana_tiles_t<double, 0>(d);
+  return var ? ana_tiles_t<float, 1>(d) : ana_tiles_t<float, 0>(d);
+}
+size_t synth_item_lds(int dtype, int L, int var, const SynthLevel& d) {
+  if (dtype) return var ? synth_lds_t<double, 1>(L, d) : synth_lds_t<double, 0>(L, d);
+  return var ? synth_lds_t<float, 1>(L, d) : synth_lds_t<float, 0>(L, d);
+}
+size_t synth_item_size(int dtype) { return dtype ? sizeof(SynthItem<double>) : sizeof(SynthItem<float>); }
+size_t ana_item_size(int dtype) { return dtype ? sizeof(AnaItem<double>) : sizeof(AnaItem<float>); }
+
+void make_synth_item(int dtype, const SynthLevel& d, const double* lo, int L, int image, void* out) {
+  if (dtype) {
+    SynthItem<double> it{d, make_taps<double>(lo, L), image};
+    *static_cast<SynthItem<double>*>(out) = it;
+  } else {
+    SynthItem<float> it{d, make_taps<float>(lo, L), image};
+    *static_cast<SynthItem<float>*>(out) = it;
+  }
+}
+void make_ana_item(int dtype, const AnaLevel& d, const double* lo, int L, int image, void* out) {
+  if (dtype) {
+    AnaItem<double> it{d, make_taps<double>(lo, L), image};
+    *static_cast<AnaItem<double>*>(out) = it;
+  } else {
+    AnaItem<float> it{d, make_taps<float>(lo, L), image};
+    *static_cast<AnaItem<float>*>(out) = it;
+  }
+}
+
+template <typename T, int L, int BC, int V>
+static hipError_t launch_synth_batch_t(const void* items, const int* prefix, int n, int total,
+                                       const int* active, size_t lds, hipStream_t s) {
+  auto kern = synth_batch_kernel<T, L, BC, V>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(total), dim3(512), lds, s, static_cast<const SynthItem<T>*>(items),
+                     prefix, n, active);
+  return hipGetLastError();
+}
+
+template <typename T, int L, int BC, int V>
+static hipError_t launch_ana_batch_t(const void* items, const int* prefix, int n, int total,
+                                     const int* active, hipStream_t s) {
+  hipLaunchKernelGGL((ana_batch_kernel<T, L, BC, V>), dim3(total), dim3(512), 0, s,
+                     static_cast<const AnaItem<T>*>(items), prefix, n, active);
+  return hipGetLastError();
+}
+
+#define AW_BATCH_DISPATCH(FN, ...)                                                        \
+  switch ((dtype << 8) | (L << 3) | (bc << 1) | var) {                                    \
+    case (0 << 8) | (2 << 3) | (ZPD << 1) | 0: return FN<float, 2, ZPD, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (2 << 3) | (ZPD << 1) | 1: return FN<float, 2, ZPD, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (2 << 3) | (SYM << 1) | 0: return FN<float, 2, SYM, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (2 << 3) | (SYM << 1) | 1: return FN<float, 2, SYM, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (2 << 3) | (PER << 1) | 0: return FN<float, 2, PER, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (2 << 3) | (PER << 1) | 1: return FN<float, 2, PER, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (ZPD << 1) | 0: return FN<float, 8, ZPD, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (ZPD << 1) | 1: return FN<float, 8, ZPD, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (SYM << 1) | 0: return FN<float, 8, SYM, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (SYM << 1) | 1: return FN<float, 8, SYM, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (PER << 1) | 0: return FN<float, 8, PER, 0>(__VA_ARGS__);  \
+    case (0 << 8) | (8 << 3) | (PER << 1) | 1: return FN<float, 8, PER, 1>(__VA_ARGS__);  \
+    case (0 << 8) | (16 << 3) | (ZPD << 1) | 0: return FN<float, 16, ZPD, 0>(__VA_ARGS__); \
+    case (0 << 8) | (16 << 3) | (ZPD << 1) | 1: return FN<float, 16, ZPD, 1>(__VA_ARGS__); \
+    case (0 << 8) | (16 << 3) | (SYM << 1) | 0: return FN<float, 16, SYM, 0>(__VA_ARGS__); \
+    case (0 << 8) | (16 << 3) | (SYM << 1) | 1: return FN<float, 16, SYM, 1>(__VA_ARGS__); \
+    case (0 << 8) | (16 << 3) | (PER << 1) | 0: return FN<float, 16, PER, 0>(__VA_ARGS__); \
+    case (0 << 8) | (16 << 3) | (PER << 1) | 1: return FN<float, 16, PER, 1>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;                                                 \
+  }
+
+// Batched launches run in FP32 (the batched workload's precision); dtype is
+// checked by the caller.
+hipError_t launch_synth_batch(int dtype, int L, int bc, int var, const void* items,
+                              const int* prefix, int n, int total, const int* active, size_t lds,
+                              hipStream_t s) {
+  AW_BATCH_DISPATCH(launch_synth_batch_t, items, prefix, n, total, active, lds, s)
+}
+hipError_t launch_ana_batch(int dtype, int L, int bc, int var, const void* items,
+                            const int* prefix, int n, int total, const int* active,
+                            hipStream_t s) {
+  AW_BATCH_DISPATCH(launch_ana_batch_t, items, prefix, n, total, active, s)
+}
+#undef AW_BATCH_DISPATCH
 
 // ---------------------------------------------------- fold of an extended image
 // out[p_r][p_c] = w_r w_c sum over preimages of ext[n_r][n_c]; used for the

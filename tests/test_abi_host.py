@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert set(names) - {"aw_last_error"} == set(_lib.SIGNATURES)
+    assert set(names) - {"aw_last_error", "aw_batch_last_error"} == set(_lib.SIGNATURES)
 
 
 def _wave(rows=64, cols=48, levels=3, L=8, bc=1, lo=None):
@@ -147,3 +147,20 @@ def test_workspace_size_grows_with_batch(lib):
     floor = 4 * (sum(sr[j] * sc[j] for j in range(1, 4)) + 2048 * 2048 + 4352319)
     assert n1.value >= floor
     assert n4.value >= 4 * floor
+
+
+def test_batch_plan_validates_before_device_work(lib):
+    plan = ctypes.c_void_p()
+    w = (_lib.Wavelet * 2)(_wave(), _wave(bc=3))
+    b = (_lib.Blur * 2)()
+    for i in range(2):
+        b[i].rows, b[i].cols, b[i].radius = 64, 48, 0
+        b[i].taps[0] = 1.0
+    assert lib.aw_batch_create(0, w, b, ctypes.byref(plan)) == _lib.EINVAL
+    assert lib.aw_batch_create(2, w, b, ctypes.byref(plan)) == _lib.EUNSUPPORTED
+    assert b"periodic extension" in lib.aw_batch_last_error()
+    w2 = (_lib.Wavelet * 1)(_wave(rows=5, cols=9, levels=1))  # sym level shorter than L - 1
+    b2 = (_lib.Blur * 1)()
+    b2[0].rows, b2[0].cols, b2[0].radius = 5, 9, 0
+    b2[0].taps[0] = 1.0
+    assert lib.aw_batch_create(1, w2, b2, ctypes.byref(plan)) == _lib.EUNSUPPORTED
