@@ -81,3 +81,24 @@ def gen_batched_config(rng: np.random.Generator, n_images: int = 64):
         out.append(dict(rows=rows, cols=cols, levels=levels, taps=taps,
                         sigma=sigma, radius=radius))
     return out
+
+
+def gen_warm_problem(rng: np.random.Generator):
+    """PSF (sigma, radius) of one warm-start training or evaluation image:
+    sigma ~ U[1, 3], radius ceil(3 sigma)."""
+    sigma = float(rng.uniform(1.0, 3.0))
+    return sigma, int(math.ceil(3.0 * sigma))
+
+
+def gen_cnn_init(rng: np.random.Generator, layers, out_scale: float = 0.1) -> np.ndarray:
+    """Initial CNN parameters, flat, layer by layer as (weight (co, ci, 3, 3),
+    bias (co,)): weights N(0, 2 / (9 ci)) (He et al. 2015), biases 0, the last
+    layer's weights further scaled by ``out_scale`` so the network starts near 0."""
+    parts = []
+    for k, (ci, co) in enumerate(layers):
+        w = rng.normal(0.0, math.sqrt(2.0 / (9.0 * ci)), size=co * ci * 9)
+        if k == len(layers) - 1:
+            w = w * out_scale
+        parts.append(w)
+        parts.append(np.zeros(co))
+    return np.concatenate(parts)
