@@ -30,6 +30,77 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpix/s for A and A* at 2048²; FISTA time-to-1e-4 rel objective, plain vs warm"
 HBM_PEAK_GBS = 8000.0
+COPY_REF_BYTES = 256 << 20  # read (and again written) by the --copy-reference kernel
+
+
+# Kernels whose HBM traffic the roofline reports: op name -> (kernel name prefix,
+# grid size at 2048^2 db4 J=4, source file whose hash the record carries).
+PMC_KERNELS = {
+    "W_level1": ("void aw::synth_level_kernel<float, 8, 1, 0>", 1048576, "wavelet.hip"),
+    "W*_level1": ("void aw::ana_level_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
+    "R": ("void aw::blur_tile_kernel<float, 7, false, 0>", 524288, "blur.hip"),
+    "R*": ("void aw::blur_tile_kernel<float, 7, true, 0>", 524288, "blur.hip"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fista2048_sym.md")
+
+
+def source_hash(name: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in (name, "aw_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1707_02018_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summary(fetch_csv: str, write_csv: str) -> None:
+    """Per-launch HBM bytes of the roofline kernels: counter averages scaled by
+    what the same counters read for the --copy-reference kernel."""
+    import csv
+
+    def load(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.setdefault((r["Kernel_Name"], int(r["Grid_Size"])), []).append(
+                    float(r["Counter_Value"]))
+        return out
+
+    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+    def avg(tab, prefix, grid):
+        v = [x for (k, g), xs in tab.items() if k.startswith(prefix) and g == grid for x in xs]
+        return sum(v) / len(v), len(v)
+
+    ref = ("void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, "
+           "float, float, at::native::binary_internal::MulFunctor<float> >", COPY_REF_BYTES // 16)
+    kib = COPY_REF_BYTES / 1024
+    ff = kib / avg(f, *ref)[0]
+    wf = kib / avg(w, *ref)[0]
+    for op, (kname, grid, src) in PMC_KERNELS.items():
+        fa, n = avg(f, kname, grid)
+        wa, _ = avg(w, kname, grid)
+        rec = {"op": op, "kernel": kname[5:], "grid": grid, "dispatches": n,
+               "fetch_kib": round(fa, 1), "write_kib": round(wa, 1),
+               "fetch_factor": round(ff, 5), "write_factor": round(wf, 5),
+               "bytes_per_launch": int(1024 * (fa * ff + wa * wf)),
+               "source": src, "source_sha": source_hash(src)}
+        print("traffic-record: " + json.dumps(rec))
+
+
+def traffic_for(op: str):
+    """HBM bytes per launch of ``op`` from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("traffic-record: "):
+            rec = json.loads(ln[len("traffic-record: "):])
+            if rec["op"] == op and rec["source_sha"] == source_hash(rec["source"]):
+                return rec["bytes_per_launch"]
+    return None
 
 
 def log(msg: str) -> None:
@@ -48,6 +119,12 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, autograd and convolution-pair sections")
     ap.add_argument("--batched-iters", type=int, default=300)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print traffic records from two rocprofv3 --pmc counter CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --copy-reference run, then exit")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="first run a plain 256 MiB copy kernel (x * 1 into y) three times, "
+                         "the known-size reference for hardware byte counters")
     return ap.parse_args()
 
 
@@ -178,6 +255,9 @@ print(json.dumps({{"sec_per_iter": dt / {iters}}}))
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(independent images shard across GPUs without exchange)",
@@ -191,6 +271,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_reference:
+        src = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     N, J, lam = args.size, 4, 2e-5
     w = ops.WaveletSpec(N, N, J, taps=8, bc=args.bc)
     bsp = ops.BlurSpec(N, N, sigma=3.0, radius=7)
@@ -276,7 +363,7 @@ def main():
                     "W_level1": "synth_level_kernel<float,8,SYM>",
                     "R": "blur_kernel<float>", "R*": "blur_adj_kernel<float>"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom),
                 "kernel": kernel_names[dom], "algorithmic_bytes": alg_bytes[dom],
                 "avg_us": round(op_us[dom], 3)}
 
