@@ -260,6 +260,76 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
                             const void* s, const void* x_obs, void* resid, void* grad_h,
                             void* grad_s, void* stream);
 
+/* ----------------------------------------------- learned warm start (CNN) */
+/* The paper solves eq. (1) by FISTA from x = 0 (Sec. "The adjoint for
+ * orthogonal wavelets"); these calls add a learned start x_0 for it, with the
+ * zero start kept as fallback. Network: six 3x3 convolution layers
+ * 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, zero 'same' padding, a bias per output
+ * channel, ReLU after the first five; a layer computes
+ *   out[o][y][x] = bias[o] + sum_{i,ky,kx} w[o][i][ky][kx] in[i][y+ky-1][x+kx-1].
+ * The image u = b + CNN(b) is mapped to coefficients by the wavelet analysis
+ * W^dagger (aw_wavelet_analysis) and x_0 = soft(W^dagger u, lambda / L)
+ * (aw_soft_threshold). Training minimises ||W^dagger u - x*||^2 (aw_sq_error),
+ * backpropagated through (W^dagger)^* (aw_wavelet_analysis_adjoint),
+ * aw_cnn_backward and aw_adam_step.
+ *
+ * Parameters  FP32 master vector of AW_CNN_PARAMS values, layer by layer, each
+ *             as weight [out][in][3][3] then bias [out].
+ * Precision   Weights and activations are rounded to BF16 (nearest even);
+ *             products accumulate in FP32 (v_mfma_f32_32x32x16_bf16 for the
+ *             32-channel layers). The input image and the incoming gradient
+ *             are rounded to BF16 where they enter a convolution; biases stay
+ *             FP32.
+ * Activations [5][batch][rows][cols][32] BF16 (uint16 bit patterns), the
+ *             outputs y_1..y_5 of layers 1..5 after ReLU (AW_CNN_ACT_BYTES per
+ *             pixel). Gradients at the pre-activations of layers 1..5 use the
+ *             same layout. */
+#define AW_CNN_CHANNELS 32
+#define AW_CNN_PARAMS 37601
+#define AW_CNN_ACT_BYTES 320 /* 5 layers x 32 channels x 2 bytes per pixel */
+
+/* Sizes: packed parameter buffer (bytes), activation buffer (bytes, also the
+ * size of the activation-gradient buffer) and the backward workspace (bytes)
+ * for `batch` images of rows x cols. Any output pointer may be NULL. */
+aw_status aw_cnn_sizes(int32_t batch, int32_t rows, int32_t cols, size_t* packed_bytes,
+                       size_t* act_bytes, size_t* workspace_bytes);
+
+/* Device-side conversion of the FP32 master parameters (AW_CNN_PARAMS) into
+ * the packed BF16 layouts the kernels read (forward and mirrored-transposed
+ * copies). Call after every parameter update. */
+aw_status aw_cnn_pack(const float* params, void* packed, void* stream);
+
+/* u = b + CNN(b) for b: [batch][rows][cols] FP32; acts receives y_1..y_5
+ * (needed by aw_cnn_backward). u must not alias b. */
+aw_status aw_cnn_forward(const void* packed, int32_t batch, int32_t rows, int32_t cols,
+                         const float* b, void* acts, float* u, void* stream);
+
+/* Gradient of <du, CNN(b)> in the parameters: grad (FP32, AW_CNN_PARAMS,
+ * overwritten, master layout) from the activations of aw_cnn_forward and du
+ * ([batch][rows][cols] FP32). dacts receives the gradients at the
+ * pre-activations of layers 1..5. Workspace size from aw_cnn_sizes.
+ * Deterministic (fixed-order reductions). */
+aw_status aw_cnn_backward(const void* packed, int32_t batch, int32_t rows, int32_t cols,
+                          const float* b, const void* acts, const float* du, void* dacts,
+                          float* grad, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adam (Kingma & Ba 2015, Algorithm 1) on n FP32 values, step t >= 1:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps). */
+aw_status aw_adam_step(float* params, float* m, float* v, const float* grad, int64_t n,
+                       int32_t step, double lr, double beta1, double beta2, double eps,
+                       void* stream);
+
+/* r = c - target over n FP32 values: grad = scale * 2 r (grad may be NULL)
+ * and *loss = sum r^2 (one FP64 device value, fixed-order sum). The
+ * workspace holds aw_sq_error_workspace(n) bytes. */
+aw_status aw_sq_error(int64_t n, const float* c, const float* target, double scale, float* grad,
+                      double* loss, void* workspace, size_t workspace_bytes, void* stream);
+aw_status aw_sq_error_workspace(int64_t n, size_t* bytes);
+
+/* out = sign(in) max(|in| - tau, 0) over n FP32 values (out may equal in). */
+aw_status aw_soft_threshold(int64_t n, const float* in, double tau, float* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

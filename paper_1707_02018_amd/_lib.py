@@ -67,6 +67,15 @@ SIGNATURES = {
     "aw_batch_control": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)],
     "aw_batch_reset": [_P, _P],
     "aw_batch_step": [_P, _P],
+    "aw_cnn_sizes": [_i32, _i32, _i32, ctypes.POINTER(_sz), ctypes.POINTER(_sz),
+                     ctypes.POINTER(_sz)],
+    "aw_cnn_pack": [_P, _P, _P],
+    "aw_cnn_forward": [_P, _i32, _i32, _i32, _P, _P, _P, _P],
+    "aw_cnn_backward": [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "aw_adam_step": [_P, _P, _P, _P, _i64, _i32, _dbl, _dbl, _dbl, _dbl, _P],
+    "aw_sq_error": [_i64, _P, _P, _dbl, _P, _P, _P, _sz, _P],
+    "aw_sq_error_workspace": [_i64, ctypes.POINTER(_sz)],
+    "aw_soft_threshold": [_i64, _P, _dbl, _P, _P],
 }
 
 _lib = None

@@ -612,4 +612,105 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
   return st == AW_OK ? ok() : st;
 }
 
+// ------------------------------------------------------- warm-start CNN
+static aw_status cnn_shape(int32_t batch, int32_t rows, int32_t cols) {
+  if (batch < 1 || rows < 1 || cols < 1)
+    return fail(AW_EINVAL, "batch=%d rows=%d cols=%d", batch, rows, cols);
+  const long long pix = (long long)batch * rows * cols;
+  if (pix > (1LL << 31) / AW_CNN_CHANNELS)
+    return fail(AW_EINVAL, "%lld pixels exceed the activation index range", pix);
+  return AW_OK;
+}
+
+aw_status aw_cnn_sizes(int32_t batch, int32_t rows, int32_t cols, size_t* packed_bytes,
+                       size_t* act_bytes, size_t* workspace_bytes) {
+  aw_status st;
+  if ((st = cnn_shape(batch, rows, cols)) != AW_OK) return st;
+  if (packed_bytes) *packed_bytes = aw::CnnPack::total;
+  if (act_bytes) *act_bytes = (size_t)batch * rows * cols * AW_CNN_ACT_BYTES;
+  if (workspace_bytes) *workspace_bytes = aw::cnn_backward_scratch(batch, rows, cols);
+  return ok();
+}
+
+aw_status aw_cnn_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed) return fail(AW_EINVAL, "NULL pointer");
+  aw_status st = hip_check(aw::launch_cnn_pack(params, packed, (hipStream_t)stream), "cnn pack");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_cnn_forward(const void* packed, int32_t batch, int32_t rows, int32_t cols,
+                         const float* b, void* acts, float* u, void* stream) {
+  aw_status st;
+  if ((st = cnn_shape(batch, rows, cols)) != AW_OK) return st;
+  if (!packed || !b || !acts || !u) return fail(AW_EINVAL, "NULL pointer");
+  if ((const void*)u == (const void*)b) return fail(AW_EINVAL, "u must not alias b");
+  st = hip_check(aw::launch_cnn_forward(packed, batch, rows, cols, b, acts, u, (hipStream_t)stream),
+                 "cnn forward");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_cnn_backward(const void* packed, int32_t batch, int32_t rows, int32_t cols,
+                          const float* b, const void* acts, const float* du, void* dacts,
+                          float* grad, void* workspace, size_t workspace_bytes, void* stream) {
+  aw_status st;
+  if ((st = cnn_shape(batch, rows, cols)) != AW_OK) return st;
+  if (!packed || !b || !acts || !du || !dacts || !grad || !workspace)
+    return fail(AW_EINVAL, "NULL pointer");
+  if (dacts == acts) return fail(AW_EINVAL, "dacts must not alias acts");
+  const size_t need = aw::cnn_backward_scratch(batch, rows, cols);
+  if (workspace_bytes < need)
+    return fail(AW_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  st = hip_check(aw::launch_cnn_backward(packed, batch, rows, cols, b, acts, du, dacts, grad,
+                                         workspace, (hipStream_t)stream),
+                 "cnn backward");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_adam_step(float* params, float* m, float* v, const float* grad, int64_t n,
+                       int32_t step, double lr, double beta1, double beta2, double eps,
+                       void* stream) {
+  if (!params || !m || !v || !grad) return fail(AW_EINVAL, "NULL pointer");
+  if (n < 1 || step < 1) return fail(AW_EINVAL, "n=%lld step=%d", (long long)n, step);
+  if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(AW_EINVAL, "lr=%g beta1=%g beta2=%g eps=%g", lr, beta1, beta2, eps);
+  const double c1 = 1.0 / (1.0 - std::pow(beta1, step));
+  const double c2 = 1.0 / (1.0 - std::pow(beta2, step));
+  aw_status st = hip_check(aw::launch_adam(params, m, v, grad, n, lr, beta1, beta2, eps, c1, c2,
+                                           (hipStream_t)stream),
+                           "adam");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_sq_error_workspace(int64_t n, size_t* bytes) {
+  if (n < 1 || !bytes) return fail(AW_EINVAL, "n=%lld", (long long)n);
+  *bytes = (size_t)aw::sq_error_blocks(n) * sizeof(double);
+  return ok();
+}
+
+aw_status aw_sq_error(int64_t n, const float* c, const float* target, double scale, float* grad,
+                      double* loss, void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 1) return fail(AW_EINVAL, "n=%lld", (long long)n);
+  if (!c || !target || !loss || !workspace) return fail(AW_EINVAL, "NULL pointer");
+  const int blocks = aw::sq_error_blocks(n);
+  if (workspace_bytes < (size_t)blocks * sizeof(double))
+    return fail(AW_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes,
+                (size_t)blocks * sizeof(double));
+  double* part = static_cast<double*>(workspace);
+  hipStream_t s = (hipStream_t)stream;
+  aw_status st = hip_check(aw::launch_sq_error(n, c, target, (float)scale, grad, part, s),
+                           "squared error");
+  if (st != AW_OK) return st;
+  st = hip_check(aw::launch_reduce_partials(1, blocks, part, 1.0, loss, 1, 0, s), "reduce");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_soft_threshold(int64_t n, const float* in, double tau, float* out, void* stream) {
+  if (n < 1 || !in || !out) return fail(AW_EINVAL, "n=%lld or NULL pointer", (long long)n);
+  if (!(tau >= 0.0)) return fail(AW_EINVAL, "tau=%g", tau);
+  aw_status st = hip_check(aw::launch_soft_threshold(n, in, (float)tau, out, (hipStream_t)stream),
+                           "soft threshold");
+  return st == AW_OK ? ok() : st;
+}
+
 }  // extern "C"

@@ -265,4 +265,48 @@ hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, c
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
                             hipStream_t st);
 
+// ------------------------------------------------------------ warm-start CNN
+// Six 3x3 layers 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 (zero 'same' padding,
+// bias, ReLU on the first five). Master parameters are FP32, one flat vector
+// layer by layer: weight [out][in][3][3] then bias [out]. Activations are BF16,
+// channels last: [image][row][col][32].
+constexpr int kCnnCh = 32;
+constexpr long long kCnnParams = 37601;
+constexpr long long kCnnMasterW1 = 0, kCnnMasterB1 = 288;
+constexpr long long cnn_master_mid(int m) { return 320 + 9248LL * m; }  // layers 2..5
+constexpr long long kCnnMasterW6 = 320 + 4 * 9248LL, kCnnMasterB6 = kCnnMasterW6 + 288;
+
+// Byte offsets of the packed (device) parameter buffer made from the master vector.
+struct CnnPack {
+  static constexpr size_t w1 = 0;                          // bf16 [9][32]: W1[c][0][t]
+  static constexpr size_t b1 = w1 + 9 * 32 * 2;             // f32 [32]
+  static constexpr size_t mid = b1 + 32 * 4;                // four mid layers
+  static constexpr size_t mid_fwd = 0;                      // bf16 [9][32 out][32 in]
+  static constexpr size_t mid_dgrad = 9 * 32 * 32 * 2;      // bf16 [9][32 in][32 out], taps mirrored
+  static constexpr size_t mid_bias = 2 * 9 * 32 * 32 * 2;   // f32 [32]
+  static constexpr size_t mid_size = mid_bias + 32 * 4;
+  static constexpr size_t w6 = mid + 4 * mid_size;          // bf16 [9][32 out][32 in], out > 0 zero
+  static constexpr size_t b6 = w6 + 9 * 32 * 32 * 2;        // f32 [32], entry 0 used
+  static constexpr size_t w6d = b6 + 32 * 4;                // bf16 [9][32]: W6[0][c][8 - t]
+  static constexpr size_t total = w6d + 9 * 32 * 2;
+};
+
+hipError_t launch_cnn_pack(const float* master, void* packed, hipStream_t s);
+hipError_t launch_cnn_forward(const void* packed, int n, int H, int W, const float* b, void* acts,
+                              float* u, hipStream_t s);
+// Scratch (bytes) of launch_cnn_backward for this shape.
+size_t cnn_backward_scratch(int n, int H, int W);
+hipError_t launch_cnn_backward(const void* packed, int n, int H, int W, const float* b,
+                               const void* acts, const float* du, void* dacts, float* grad,
+                               void* scratch, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, long long n, double lr,
+                       double beta1, double beta2, double eps, double c1, double c2,
+                       hipStream_t s);
+// grad = scale * 2 (c - t) (if grad != null); partials[b] = FP64 block sums of (c - t)^2
+int sq_error_blocks(long long n);
+hipError_t launch_sq_error(long long n, const float* c, const float* t, float scale, float* grad,
+                           double* partials, hipStream_t s);
+hipError_t launch_soft_threshold(long long n, const float* in, float tau, float* out,
+                                 hipStream_t s);
+
 }  // namespace aw

@@ -1,0 +1,804 @@
+// Warm-start CNN on gfx950: BF16 operands, FP32 accumulation.
+//
+// The 32 -> 32 layers (and the 32 -> 1 output layer, zero-padded to 32
+// outputs) are implicit GEMMs on v_mfma_f32_32x32x16_bf16 with M = 32 output
+// channels, N = 32 pixels of one image row, K = 16 input channels per tap half.
+// Each wave owns a 32-pixel column strip and slides down its rows: one input
+// row's three shifted fragments feed the three output rows that need them, so
+// every fragment is loaded once and used by three taps. The weights of all
+// nine taps stay in registers for the whole strip. The same kernel runs the
+// input gradient (mirrored, transposed weights) with the ReLU mask of the
+// layer below applied in its epilogue.
+//
+// The weight gradient is a K = pixels contraction, so both operands are
+// staged through LDS transposed to channel-major rows; the three horizontal
+// tap shifts come from one aligned 16-byte read plus byte alignment.
+//
+// The 1 -> 32 input layer and the 32 -> 1 input gradient are VALU (nine
+// products per output), as is the weight gradient of those two layers.
+// Every reduction is fixed-order: results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "aw_internal.hpp"
+
+namespace aw {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float bf2f(unsigned h) { return __uint_as_float(h << 16); }
+
+// Round to nearest even; NaN stays a (quiet) NaN.
+__device__ __forceinline__ unsigned f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bool bf_positive(unsigned h) { return !(h & 0x8000u) && (h & 0x7fffu); }
+
+__device__ __forceinline__ float rnd_bf(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ u32x4 ld16(const uint16_t* p) {
+  return *reinterpret_cast<const u32x4*>(p);
+}
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// ----------------------------------------------------------------- packing
+__global__ void cnn_pack_kernel(const float* __restrict__ m, uint8_t* __restrict__ pk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int nW1 = 288, nB = 32, nMid = 9216;
+  int r = i;
+  if (r < nW1) {  // w1[t][c] = W1[c][0][t]
+    const int t = r / 32, c = r % 32;
+    reinterpret_cast<uint16_t*>(pk + CnnPack::w1)[r] = f2bf(m[kCnnMasterW1 + c * 9 + t]);
+    return;
+  }
+  r -= nW1;
+  if (r < nB) {
+    reinterpret_cast<float*>(pk + CnnPack::b1)[r] = m[kCnnMasterB1 + r];
+    return;
+  }
+  r -= nB;
+  for (int l = 0; l < 4; ++l) {
+    const long long base = cnn_master_mid(l);
+    uint8_t* L = pk + CnnPack::mid + l * CnnPack::mid_size;
+    if (r < nMid) {  // fwd[t][o][i] = W[o][i][t]
+      const int t = r / 1024, o = (r / 32) % 32, c = r % 32;
+      reinterpret_cast<uint16_t*>(L + CnnPack::mid_fwd)[r] = f2bf(m[base + (o * 32 + c) * 9 + t]);
+      return;
+    }
+    r -= nMid;
+    if (r < nMid) {  // dgrad[t][i][o] = W[o][i][8 - t]
+      const int t = r / 1024, c = (r / 32) % 32, o = r % 32;
+      reinterpret_cast<uint16_t*>(L + CnnPack::mid_dgrad)[r] =
+          f2bf(m[base + (o * 32 + c) * 9 + (8 - t)]);
+      return;
+    }
+    r -= nMid;
+    if (r < nB) {
+      reinterpret_cast<float*>(L + CnnPack::mid_bias)[r] = m[base + 9216 + r];
+      return;
+    }
+    r -= nB;
+  }
+  if (r < nMid) {  // w6[t][o][i]: output 0 only
+    const int t = r / 1024, o = (r / 32) % 32, c = r % 32;
+    reinterpret_cast<uint16_t*>(pk + CnnPack::w6)[r] =
+        o == 0 ? f2bf(m[kCnnMasterW6 + c * 9 + t]) : 0u;
+    return;
+  }
+  r -= nMid;
+  if (r < nB) {
+    reinterpret_cast<float*>(pk + CnnPack::b6)[r] = r == 0 ? m[kCnnMasterB6] : 0.0f;
+    return;
+  }
+  r -= nB;
+  if (r < nW1) {  // w6d[t][c] = W6[0][c][8 - t]
+    const int t = r / 32, c = r % 32;
+    reinterpret_cast<uint16_t*>(pk + CnnPack::w6d)[r] = f2bf(m[kCnnMasterW6 + c * 9 + (8 - t)]);
+  }
+}
+constexpr int kPackJobs = 288 + 32 + 4 * (2 * 9216 + 32) + 9216 + 32 + 288;
+
+// ------------------------------------------------------- 1 -> 32 (VALU)
+// y[p][c] = sum_t w[t][c] rnd(src[p + off(t)])   (+ bias, ReLU)   or   (* [mask > 0])
+// One thread per (pixel, group of 8 channels); off(t) = (t / 3 - 1, t % 3 - 1).
+template <bool FWD>
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ src,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias,
+                                                      const uint16_t* __restrict__ mask,
+                                                      uint16_t* __restrict__ y, int H, int W,
+                                                      long long npix) {
+  const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long p = gid >> 2;
+  const int g = (int)(gid & 3);
+  if (p >= npix) return;
+  const int x = (int)(p % W);
+  const long long q = p / W;
+  const int r = (int)(q % H);
+  const float* s = src + (q / H) * (long long)H * W;
+  float in[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
+    in[t] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? rnd_bf(s[(long long)rr * W + cc]) : 0.0f;
+  }
+  float acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = FWD ? bias[8 * g + j] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const u32x4 wv = ld16(w + t * 32 + 8 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[2 * j] += bf2f(wv[j] & 0xffffu) * in[t];
+      acc[2 * j + 1] += bf2f(wv[j] >> 16) * in[t];
+    }
+  }
+  u32x4 mk = {0, 0, 0, 0};
+  if (!FWD) mk = ld16(mask + p * 32 + 8 * g);
+  u32x4 out;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float a0 = acc[2 * j], a1 = acc[2 * j + 1];
+    if (FWD) {
+      a0 = fmaxf(a0, 0.0f);
+      a1 = fmaxf(a1, 0.0f);
+    } else {
+      if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
+      if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
+    }
+    out[j] = f2bf(a0) | (f2bf(a1) << 16);
+  }
+  *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
+}
+
+// ------------------------------------------------------- 32 -> 32 (MFMA)
+enum ConvMode { kFwd = 0, kDgrad = 1, kOut = 2 };
+
+struct ConvArgs {
+  const uint16_t* x;     // [n][H][W][32]
+  const uint16_t* w;     // [9][32 out][32 in]
+  const float* bias;     // [32] (kFwd, kOut)
+  const uint16_t* mask;  // [n][H][W][32] (kDgrad)
+  uint16_t* y;           // [n][H][W][32] (kFwd, kDgrad)
+  const float* base;     // [n][H][W] (kOut): added to output channel 0
+  float* out;            // [n][H][W] (kOut)
+  int H, W, strips, bands, total_waves;
+};
+
+constexpr int kConvR = 16;  // output rows per wave; (kConvR + 2) % 3 == 0
+static_assert((kConvR + 2) % 3 == 0, "row loop is unrolled by three");
+
+struct Frags {
+  u32x4 f[3][2];  // [kx][k half]
+};
+
+template <int I>
+__device__ __forceinline__ f32x16& pick(f32x16& a, f32x16& b, f32x16& c) {
+  if constexpr (I == 0) return a;
+  else if constexpr (I == 1) return b;
+  else return c;
+}
+
+__device__ __forceinline__ void load_row(Frags& F, const uint16_t* X, int H, int W, int r, int x,
+                                         int h) {
+  const bool rv = r >= 0 && r < H;
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    const int c = x + kx - 1;
+    const bool v = rv && c >= 0 && c < W;
+    const uint16_t* p = X + ((long long)r * W + c) * 32 + 8 * h;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) F.f[kx][kb] = v ? ld16(p + 16 * kb) : u32x4{0, 0, 0, 0};
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, long long img_off,
+                                              int o, int x, int h) {
+  if (x < a.W) {
+    const long long pix = img_off + (long long)o * a.W + x;
+    if constexpr (MODE == kOut) {
+      if (h == 0) a.out[pix] = acc[0] + a.bias[0] + a.base[pix];
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co = 8 * g + 4 * h;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = acc[4 * g + i];
+        if constexpr (MODE == kFwd) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i] + a.bias[co + i], 0.0f);
+        } else {
+          const u32x2 mk = *reinterpret_cast<const u32x2*>(a.mask + pix * 32 + co);
+          if (!bf_positive(mk[0] & 0xffffu)) v[0] = 0.0f;
+          if (!bf_positive(mk[0] >> 16)) v[1] = 0.0f;
+          if (!bf_positive(mk[1] & 0xffffu)) v[2] = 0.0f;
+          if (!bf_positive(mk[1] >> 16)) v[3] = 0.0f;
+        }
+        u32x2 st;
+        st[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
+        st[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
+        *reinterpret_cast<u32x2*>(a.y + pix * 32 + co) = st;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+}
+
+// The three taps of kernel row KY on one input row's fragments.
+template <int KY>
+__device__ __forceinline__ void conv_taps(const bf16x8 (&wa)[9][2], const Frags& cur, f32x16& acc) {
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[KY * 3 + kx][kb], as_bf(cur.f[kx][kb]), acc,
+                                                    0, 0, 0);
+}
+
+// One input row r (S = (r - y0 + 1) mod 3): contributions to output rows
+// r + 1 (ky = 0), r (ky = 1), r - 1 (ky = 2); row r - 1 is then complete.
+template <int MODE, int S>
+__device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, long long img_off,
+                                         const bf16x8 (&wa)[9][2], Frags& nxt, f32x16& a0,
+                                         f32x16& a1, f32x16& a2, int r, int y0, int yend, int x,
+                                         int h) {
+  Frags cur = nxt;
+  if (r + 1 <= yend) load_row(nxt, X, a.H, a.W, r + 1, x, h);
+  if (r >= 0 && r < a.H) {
+    if (r + 1 < yend) conv_taps<0>(wa, cur, pick<S>(a0, a1, a2));
+    if (r >= y0 && r < yend) conv_taps<1>(wa, cur, pick<(S + 2) % 3>(a0, a1, a2));
+    if (r - 1 >= y0 && r - 1 < yend) conv_taps<2>(wa, cur, pick<(S + 1) % 3>(a0, a1, a2));
+  }
+  const int o = r - 1;
+  f32x16& done = pick<(S + 1) % 3>(a0, a1, a2);
+  if (o >= y0 && o < yend) conv_epilogue<MODE>(a, done, img_off, o, x, h);
+  else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) done[i] = 0.0f;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void conv32_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= a.total_waves) return;  // whole waves only
+  const int sx = wave % a.strips;
+  const int rest = wave / a.strips;
+  const int band = rest % a.bands;
+  const int img = rest / a.bands;
+  const int h = lane >> 5;
+  const int x = sx * 32 + (lane & 31);
+  const int y0 = band * kConvR;
+  const int yend = min(y0 + kConvR, a.H);
+  const long long img_off = (long long)img * a.H * a.W;
+  const uint16_t* X = a.x + img_off * 32;
+
+  bf16x8 wa[9][2];
+  {
+    const uint16_t* wp = a.w + (lane & 31) * 32 + 8 * h;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) wa[t][kb] = as_bf(ld16(wp + t * 1024 + 16 * kb));
+  }
+  f32x16 a0, a1, a2;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a0[i] = a1[i] = a2[i] = 0.0f;
+  Frags nxt;
+  load_row(nxt, X, a.H, a.W, y0 - 1, x, h);
+  for (int r = y0 - 1; r <= yend; r += 3) {
+    conv_row<MODE, 0>(a, X, img_off, wa, nxt, a0, a1, a2, r, y0, yend, x, h);
+    conv_row<MODE, 1>(a, X, img_off, wa, nxt, a0, a1, a2, r + 1, y0, yend, x, h);
+    conv_row<MODE, 2>(a, X, img_off, wa, nxt, a0, a1, a2, r + 2, y0, yend, x, h);
+  }
+}
+
+// --------------------------------------------- 32 -> 32 weight gradient
+// part[wg][(o * 32 + i) * 9 + t] = sum over the tile's pixels p of
+//   dz[p][o] * x[p + off(t)][i];   part[wg][9216 + o] = sum_p dz[p][o].
+constexpr int kWgSW = 128;              // strip width (pixels): 4 waves x 2 chunks of 16
+constexpr int kWgPD = kWgSW + 8;        // dz^T row pitch (elements)
+constexpr int kWgPY = kWgSW + 24;       // x^T row pitch: columns x0 - 8 .. x0 + SW + 7
+constexpr int kWgPairsY = (kWgSW + 16) / 2;
+constexpr int kWgLds = 32 * kWgPD + 3 * 32 * kWgPY;  // elements
+constexpr int kWgWidth = 9248;
+static_assert(kWgLds * 2 >= 9216 * 4, "reduction buffer reuses the staging LDS");
+static_assert(kWgLds * 2 >= 256 * 8 * 4, "bias reduction reuses the staging LDS");
+
+struct WgradArgs {
+  const uint16_t* dz;
+  const uint16_t* x;
+  float* part;
+  int H, W, strips, bands, RB;
+};
+
+__device__ __forceinline__ u32x4 load_chunk(const uint16_t* P, int H, int W, int r, int c, int g) {
+  if (r < 0 || r >= H || c < 0 || c >= W) return u32x4{0, 0, 0, 0};
+  return ld16(P + ((long long)r * W + c) * 32 + 8 * g);
+}
+
+// Channels 8g..8g+7 of pixels col and col + 1 -> eight channel-major rows.
+__device__ __forceinline__ void put_pair(uint16_t* T, int pitch, int col, int g, u32x4 a, u32x4 b) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned lo = (a[i] & 0xffffu) | (b[i] << 16);
+    const unsigned hi = (a[i] >> 16) | (b[i] & 0xffff0000u);
+    *reinterpret_cast<unsigned*>(T + (8 * g + 2 * i) * pitch + col) = lo;
+    *reinterpret_cast<unsigned*>(T + (8 * g + 2 * i + 1) * pitch + col) = hi;
+  }
+}
+
+__global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[kWgLds];
+  uint16_t* dzT = lds;
+  uint16_t* xT = lds + 32 * kWgPD;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int wg = blockIdx.x;
+  const int sx = wg % a.strips;
+  const int rest = wg / a.strips;
+  const int band = rest % a.bands;
+  const int img = rest / a.bands;
+  const int x0 = sx * kWgSW, y0 = band * a.RB, y1 = min(y0 + a.RB, a.H);
+  const long long plane = (long long)a.H * a.W * 32;
+  const uint16_t* DZ = a.dz + img * plane;
+  const uint16_t* XS = a.x + img * plane;
+  const int pp = tid >> 2, g = tid & 3;  // staging job: pixel pair, channel group
+
+  float bsum[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bsum[j] = 0.0f;
+  f32x16 acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+
+  // x rows y0 - 1 and y0 into slots 0 and 1
+  for (int s = 0; s < 2; ++s)
+    for (int j = tid; j < kWgPairsY * 4; j += 256) {
+      const int q = j >> 2, gg = j & 3, c = x0 - 8 + 2 * q;
+      const u32x4 u0 = load_chunk(XS, a.H, a.W, y0 - 1 + s, c, gg);
+      const u32x4 u1 = load_chunk(XS, a.H, a.W, y0 - 1 + s, c + 1, gg);
+      put_pair(xT + s * 32 * kWgPY, kWgPY, 2 * q, gg, u0, u1);
+    }
+
+  for (int o = y0; o < y1; ++o) {
+    const u32x4 d0 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp, g);
+    const u32x4 d1 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp + 1, g);
+    u32x4 e0[2], e1[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int j = tid + 256 * k;
+      const int q = j >> 2, gg = j & 3, c = x0 - 8 + 2 * q;
+      const bool on = j < kWgPairsY * 4;
+      e0[k] = on ? load_chunk(XS, a.H, a.W, o + 1, c, gg) : u32x4{0, 0, 0, 0};
+      e1[k] = on ? load_chunk(XS, a.H, a.W, o + 1, c + 1, gg) : u32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bsum[2 * i] += bf2f(d0[i] & 0xffffu) + bf2f(d1[i] & 0xffffu);
+      bsum[2 * i + 1] += bf2f(d0[i] >> 16) + bf2f(d1[i] >> 16);
+    }
+    const int s0 = (o - y0) % 3;  // slot of row o - 1
+    const int snew = (s0 + 2) % 3;
+    __syncthreads();  // the previous row's reads are done
+    put_pair(dzT, kWgPD, 2 * pp, g, d0, d1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int j = tid + 256 * k;
+      if (j < kWgPairsY * 4) put_pair(xT + snew * 32 * kWgPY, kWgPY, 2 * (j >> 2), j & 3, e0[k], e1[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int k0 = (wv * 2 + c) * 16;
+      const bf16x8 A = as_bf(*reinterpret_cast<const u32x4*>(dzT + l32 * kWgPD + k0 + 8 * h));
+      const int E = k0 + 8 * h + 8;
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        const uint16_t* row = xT + ((s0 + ky) % 3) * 32 * kWgPY + l32 * kWgPY;
+        const u32x4 d = *reinterpret_cast<const u32x4*>(row + E);
+        const unsigned pv = *reinterpret_cast<const unsigned*>(row + E - 2);
+        const unsigned nv = *reinterpret_cast<const unsigned*>(row + E + 8);
+        u32x4 b0, b2;
+        b0[0] = __builtin_amdgcn_alignbyte(d[0], pv, 2);
+        b0[1] = __builtin_amdgcn_alignbyte(d[1], d[0], 2);
+        b0[2] = __builtin_amdgcn_alignbyte(d[2], d[1], 2);
+        b0[3] = __builtin_amdgcn_alignbyte(d[3], d[2], 2);
+        b2[0] = b0[1];
+        b2[1] = b0[2];
+        b2[2] = b0[3];
+        b2[3] = __builtin_amdgcn_alignbyte(nv, d[3], 2);
+        acc[3 * ky] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, as_bf(b0), acc[3 * ky], 0, 0, 0);
+        acc[3 * ky + 1] =
+            __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, as_bf(d), acc[3 * ky + 1], 0, 0, 0);
+        acc[3 * ky + 2] =
+            __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, as_bf(b2), acc[3 * ky + 2], 0, 0, 0);
+      }
+    }
+  }
+
+  float* part = a.part + (long long)wg * kWgWidth;
+  float* red = reinterpret_cast<float*>(lds);
+  __syncthreads();
+  // bias sums: threads sharing a channel group, fixed order
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[tid * 8 + j] = bsum[j];
+  __syncthreads();
+  if (tid < 32) {
+    const int gg = tid >> 3, j = tid & 7;
+    float s = 0.0f;
+    for (int q = 0; q < 64; ++q) s += red[(q * 4 + gg) * 8 + j];
+    part[9216 + tid] = s;
+  }
+  __syncthreads();
+  // weight sums over the four waves, fixed order
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int co = 8 * (v >> 2) + 4 * h + (v & 3);
+          const int idx = t * 1024 + co * 32 + l32;
+          red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[t][v];
+        }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < 9216; idx += 256) {
+    const int co = idx / 288, rem = idx - co * 288, ci = rem / 9, t = rem - ci * 9;
+    part[idx] = red[t * 1024 + co * 32 + ci];
+  }
+}
+
+// ------------------------------ 1-channel weight gradients (VALU)
+// out[c][t] = sum_p X32[p][c] rnd(x1[p + off(t)]) (stored at c * 9 + (flip ? 8 - t : t)),
+// out[288 + c] = sum_p X32[p][c] (width 320)  or  out[288] = sum_p x1[p] (width 289).
+constexpr int kWinPix = 4096;  // pixels per workgroup
+
+__global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restrict__ X32,
+                                                       const float* __restrict__ x1,
+                                                       float* __restrict__ part, int H, int W,
+                                                       long long npix, int flip, int width) {
+  __shared__ float red[4][4][81];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = tid & 3;
+  float acc[72], s32[8], s1 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 72; ++i) acc[i] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s32[j] = 0.0f;
+  const long long p0 = (long long)blockIdx.x * kWinPix;
+  const long long p1 = min(p0 + kWinPix, npix);
+  for (long long p = p0 + (tid >> 2); p < p1; p += 64) {
+    const int x = (int)(p % W);
+    const long long q = p / W;
+    const int r = (int)(q % H);
+    const float* s = x1 + (q / H) * (long long)H * W;
+    float in[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
+      in[t] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? rnd_bf(s[(long long)rr * W + cc]) : 0.0f;
+    }
+    const u32x4 v = ld16(X32 + p * 32 + 8 * g);
+    float xv[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      xv[2 * j] = bf2f(v[j] & 0xffffu);
+      xv[2 * j + 1] = bf2f(v[j] >> 16);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s32[j] += xv[j];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t];
+    }
+    if (g == 0) s1 += s[(long long)r * W + x];
+  }
+  // lanes with the same g: reduce over lane bits 2..5 (fixed pattern)
+#pragma unroll
+  for (int i = 0; i < 72; ++i)
+    for (int m = 4; m < 64; m <<= 1) acc[i] += __shfl_xor(acc[i], m);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    for (int m = 4; m < 64; m <<= 1) s32[j] += __shfl_xor(s32[j], m);
+  for (int m = 4; m < 64; m <<= 1) s1 += __shfl_xor(s1, m);
+  if (lane < 4) {
+#pragma unroll
+    for (int i = 0; i < 72; ++i) red[wv][g][i] = acc[i];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[wv][g][72 + j] = s32[j];
+    red[wv][g][80] = s1;
+  }
+  __syncthreads();
+  float* out = part + (long long)blockIdx.x * width;
+  for (int i = tid; i < width; i += 256) {
+    float v = 0.0f;
+    if (i < 288) {
+      const int c = i / 9, tt = i % 9, t = flip ? 8 - tt : tt;
+      for (int w = 0; w < 4; ++w) v += red[w][c >> 3][(c & 7) * 9 + t];
+    } else if (width == 320) {
+      const int c = i - 288;
+      for (int w = 0; w < 4; ++w) v += red[w][c >> 3][72 + (c & 7)];
+    } else {
+      for (int w = 0; w < 4; ++w) v += red[w][0][80];
+    }
+    out[i] = v;
+  }
+}
+
+// ------------------------------------------------ column sums of partials
+// out[j] = sum_r part[r][j], rows in fixed order (two stages, FP64).
+constexpr int kRedRows = 32;
+
+__global__ void col_sum_stage1(const float* __restrict__ part, int nrows, int width,
+                               double* __restrict__ tmp) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= width) return;
+  const int r0 = blockIdx.y * kRedRows, r1 = min(r0 + kRedRows, nrows);
+  double s = 0.0;
+  for (int r = r0; r < r1; ++r) s += part[(long long)r * width + j];
+  tmp[(long long)blockIdx.y * width + j] = s;
+}
+
+__global__ void col_sum_stage2(const double* __restrict__ tmp, int nchunks, int width,
+                               float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= width) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += tmp[(long long)c * width + j];
+  out[j] = (float)s;
+}
+
+// ---------------------------------------------------------------- others
+// b1, b2 and their complements (computed in FP64 on the host: 1 - 0.999f
+// would lose four digits) enter separately.
+__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, long long n, float lr, float b1, float b2,
+                            float omb1, float omb2, float eps, float c1, float c2) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+constexpr int kSqBlock = 256, kSqPerThread = 16;
+
+__global__ __launch_bounds__(kSqBlock) void sq_error_kernel(long long n, const float* __restrict__ c,
+                                                            const float* __restrict__ t, float scale,
+                                                            float* __restrict__ grad,
+                                                            double* __restrict__ partials) {
+  __shared__ double red[kSqBlock];
+  const long long base = (long long)blockIdx.x * kSqBlock * kSqPerThread;
+  double s = 0.0;
+  for (int k = 0; k < kSqPerThread; ++k) {
+    const long long i = base + (long long)k * kSqBlock + threadIdx.x;
+    if (i < n) {
+      const float r = c[i] - t[i];
+      if (grad) grad[i] = scale * 2.0f * r;
+      s += (double)r * r;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kSqBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void soft_kernel(long long n, const float* __restrict__ in, float tau,
+                            float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float v = in[i];
+  const float a = fabsf(v) - tau;
+  out[i] = a > 0.0f ? copysignf(a, v) : 0.0f;
+}
+
+// ------------------------------------------------------------ host side
+ConvArgs conv_args(int n, int H, int W) {
+  ConvArgs a{};
+  a.H = H;
+  a.W = W;
+  a.strips = (W + 31) / 32;
+  a.bands = (H + kConvR - 1) / kConvR;
+  a.total_waves = n * a.strips * a.bands;
+  return a;
+}
+
+template <int MODE>
+hipError_t launch_conv32(const ConvArgs& a, hipStream_t s) {
+  const int blocks = (a.total_waves + 3) / 4;
+  hipLaunchKernelGGL(conv32_kernel<MODE>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_in(bool fwd, const float* src, const uint16_t* w, const float* bias,
+                          const uint16_t* mask, uint16_t* y, int n, int H, int W, hipStream_t s) {
+  const long long npix = (long long)n * H * W;
+  const long long blocks = (npix * 4 + 255) / 256;
+  if (fwd)
+    hipLaunchKernelGGL(conv_in_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, src, w, bias,
+                       mask, y, H, W, npix);
+  else
+    hipLaunchKernelGGL(conv_in_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, src, w,
+                       bias, mask, y, H, W, npix);
+  return hipGetLastError();
+}
+
+struct WgradPlan {
+  int strips, bands, RB, nwg;
+};
+
+WgradPlan wgrad_plan(int n, int H, int W) {
+  WgradPlan p{};
+  p.strips = (W + kWgSW - 1) / kWgSW;
+  const int per = n * p.strips;
+  const int want = 1024;  // about four workgroups per compute unit
+  int bands = (want + per - 1) / per;
+  bands = bands < 1 ? 1 : (bands > H ? H : bands);
+  p.RB = (H + bands - 1) / bands;
+  p.bands = (H + p.RB - 1) / p.RB;
+  p.nwg = per * p.bands;
+  return p;
+}
+
+long long win_blocks(int n, int H, int W) {
+  return ((long long)n * H * W + kWinPix - 1) / kWinPix;
+}
+
+hipError_t col_sum(const float* part, int nrows, int width, double* tmp, float* out,
+                   hipStream_t s) {
+  const int chunks = (nrows + kRedRows - 1) / kRedRows;
+  const int bx = (width + 255) / 256;
+  hipLaunchKernelGGL(col_sum_stage1, dim3(bx, chunks), dim3(256), 0, s, part, nrows, width, tmp);
+  hipLaunchKernelGGL(col_sum_stage2, dim3(bx), dim3(256), 0, s, tmp, chunks, width, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cnn_pack(const float* master, void* packed, hipStream_t s) {
+  hipLaunchKernelGGL(cnn_pack_kernel, dim3((kPackJobs + 255) / 256), dim3(256), 0, s, master,
+                     static_cast<uint8_t*>(packed));
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_forward(const void* packed, int n, int H, int W, const float* b, void* acts,
+                              float* u, hipStream_t s) {
+  const uint8_t* pk = static_cast<const uint8_t*>(packed);
+  uint16_t* A = static_cast<uint16_t*>(acts);
+  const long long layer = (long long)n * H * W * kCnnCh;
+  hipError_t e = launch_conv_in(true, b, reinterpret_cast<const uint16_t*>(pk + CnnPack::w1),
+                                reinterpret_cast<const float*>(pk + CnnPack::b1), nullptr, A, n, H,
+                                W, s);
+  if (e != hipSuccess) return e;
+  for (int m = 0; m < 4; ++m) {
+    const uint8_t* L = pk + CnnPack::mid + m * CnnPack::mid_size;
+    ConvArgs a = conv_args(n, H, W);
+    a.x = A + m * layer;
+    a.w = reinterpret_cast<const uint16_t*>(L + CnnPack::mid_fwd);
+    a.bias = reinterpret_cast<const float*>(L + CnnPack::mid_bias);
+    a.y = A + (m + 1) * layer;
+    if ((e = launch_conv32<kFwd>(a, s)) != hipSuccess) return e;
+  }
+  ConvArgs a = conv_args(n, H, W);
+  a.x = A + 4 * layer;
+  a.w = reinterpret_cast<const uint16_t*>(pk + CnnPack::w6);
+  a.bias = reinterpret_cast<const float*>(pk + CnnPack::b6);
+  a.base = b;
+  a.out = u;
+  return launch_conv32<kOut>(a, s);
+}
+
+size_t cnn_backward_scratch(int n, int H, int W) {
+  const WgradPlan p = wgrad_plan(n, H, W);
+  const long long rows = p.nwg > win_blocks(n, H, W) ? p.nwg : win_blocks(n, H, W);
+  const size_t part = (size_t)rows * kWgWidth * sizeof(float);
+  const size_t tmp = (size_t)((rows + kRedRows - 1) / kRedRows) * kWgWidth * sizeof(double);
+  return ((part + 255) / 256) * 256 + tmp;
+}
+
+hipError_t launch_cnn_backward(const void* packed, int n, int H, int W, const float* b,
+                               const void* acts, const float* du, void* dacts, float* grad,
+                               void* scratch, hipStream_t s) {
+  const uint8_t* pk = static_cast<const uint8_t*>(packed);
+  const uint16_t* A = static_cast<const uint16_t*>(acts);
+  uint16_t* D = static_cast<uint16_t*>(dacts);
+  const long long layer = (long long)n * H * W * kCnnCh;
+  const long long npix = (long long)n * H * W;
+  const WgradPlan wp = wgrad_plan(n, H, W);
+  const long long wb = win_blocks(n, H, W);
+  const long long rows = wp.nwg > wb ? wp.nwg : wb;
+  float* part = static_cast<float*>(scratch);
+  double* tmp = reinterpret_cast<double*>(static_cast<uint8_t*>(scratch) +
+                                          ((size_t)rows * kWgWidth * sizeof(float) + 255) / 256 * 256);
+  hipError_t e;
+  // output layer: weights, then the gradient at layer 5's pre-activation
+  hipLaunchKernelGGL(wgrad_in_kernel, dim3((unsigned)wb), dim3(256), 0, s, A + 4 * layer, du, part,
+                     H, W, npix, 1, 289);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = col_sum(part, (int)wb, 289, tmp, grad + kCnnMasterW6, s)) != hipSuccess) return e;
+  if ((e = launch_conv_in(false, du, reinterpret_cast<const uint16_t*>(pk + CnnPack::w6d), nullptr,
+                          A + 4 * layer, D + 4 * layer, n, H, W, s)) != hipSuccess)
+    return e;
+  for (int m = 3; m >= 0; --m) {  // layer m + 2: input acts[m], output gradient dacts[m + 1]
+    WgradArgs g{};
+    g.dz = D + (m + 1) * layer;
+    g.x = A + m * layer;
+    g.part = part;
+    g.H = H;
+    g.W = W;
+    g.strips = wp.strips;
+    g.bands = wp.bands;
+    g.RB = wp.RB;
+    hipLaunchKernelGGL(wgrad32_kernel, dim3(wp.nwg), dim3(256), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = col_sum(part, wp.nwg, kWgWidth, tmp, grad + cnn_master_mid(m), s)) != hipSuccess)
+      return e;
+    const uint8_t* L = pk + CnnPack::mid + m * CnnPack::mid_size;
+    ConvArgs a = conv_args(n, H, W);
+    a.x = D + (m + 1) * layer;
+    a.w = reinterpret_cast<const uint16_t*>(L + CnnPack::mid_dgrad);
+    a.mask = A + m * layer;
+    a.y = D + m * layer;
+    if ((e = launch_conv32<kDgrad>(a, s)) != hipSuccess) return e;
+  }
+  // input layer: weights only (no gradient is needed at the image)
+  hipLaunchKernelGGL(wgrad_in_kernel, dim3((unsigned)wb), dim3(256), 0, s, D, b, part, H, W, npix, 0,
+                     320);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return col_sum(part, (int)wb, 320, tmp, grad + kCnnMasterW1, s);
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, long long n, double lr,
+                       double beta1, double beta2, double eps, double c1, double c2,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, m, v, g, n,
+                     (float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1),
+                     (float)(1.0 - beta2), (float)eps, (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+int sq_error_blocks(long long n) {
+  const long long per = (long long)kSqBlock * kSqPerThread;
+  return (int)((n + per - 1) / per);
+}
+
+hipError_t launch_sq_error(long long n, const float* c, const float* t, float scale, float* grad,
+                           double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(sq_error_kernel, dim3(sq_error_blocks(n)), dim3(kSqBlock), 0, s, n, c, t, scale,
+                     grad, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_threshold(long long n, const float* in, float tau, float* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(soft_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, tau,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace aw

@@ -1,0 +1,373 @@
+"""Learned warm start for FISTA on eq. (1).
+
+A six-layer 3x3 CNN (1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU, BF16
+weights and activations, FP32 accumulation on MFMA) maps the blurred image b
+to u = b + CNN(b); the start is x_0 = soft(W^dagger u, lambda / L), where
+W^dagger is the wavelet analysis (the left inverse of the synthesis W). FISTA
+from zero stays the fallback: x_0 is rejected when it is not finite or when
+F(x_0) > F(0) = 1/2 ||b||^2.
+
+Training minimises the mean of (W^dagger u - x*)^2 over pairs (b, x*) whose x*
+comes from running this library's FISTA on b; the gradient reaches the image
+through (W^dagger)^* and the network through its backward kernels, and Adam
+updates FP32 master weights. Every step runs in the library's kernels; torch
+holds device memory only.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import ops
+from .batched import BatchedFista
+
+LAYERS = [(1, 32)] + [(32, 32)] * 4 + [(32, 1)]
+
+
+def init_params(seed: int, out_scale: float = 0.1) -> np.ndarray:
+    """He-normal weights, zero biases; the output layer scaled down so the
+    untrained network starts near u = b."""
+    rng = np.random.default_rng((31, int(seed)))
+    parts = []
+    for k, (ci, co) in enumerate(LAYERS):
+        w = rng.normal(0.0, math.sqrt(2.0 / (9.0 * ci)), size=co * ci * 9)
+        parts += [w * (out_scale if k == len(LAYERS) - 1 else 1.0), np.zeros(co)]
+    return np.concatenate(parts)
+
+
+class WarmStartCNN:
+    """FP32 master parameters with Adam state, and their packed BF16 copy."""
+
+    def __init__(self, device="cuda:0", params: np.ndarray | None = None, seed: int = 0):
+        self.device = torch.device(device)
+        p = init_params(seed) if params is None else np.asarray(params)
+        if p.size != ops.CNN_PARAMS:
+            raise ValueError(f"{ops.CNN_PARAMS} parameters expected, got {p.size}")
+        self.params = torch.tensor(p, dtype=torch.float32, device=self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        pk, _, _ = ops.cnn_sizes(1, 1, 1)
+        self.packed = torch.empty(pk, dtype=torch.uint8, device=self.device)
+        self.grad = torch.zeros_like(self.params)
+        self._bufs = {}
+        self.pack()
+
+    def pack(self) -> None:
+        ops.cnn_pack(self.params, self.packed)
+
+    def _buffers(self, n, H, W):
+        key = (n, H, W)
+        if key not in self._bufs:
+            _, act, ws = ops.cnn_sizes(n, H, W)
+            dev = self.device
+            self._bufs[key] = {
+                "acts": torch.empty(act, dtype=torch.uint8, device=dev),
+                "dacts": torch.empty(act, dtype=torch.uint8, device=dev),
+                "ws": torch.empty(ws, dtype=torch.uint8, device=dev),
+                "u": torch.empty(n, H, W, dtype=torch.float32, device=dev),
+            }
+        return self._bufs[key]
+
+    def forward(self, b: torch.Tensor) -> torch.Tensor:
+        """u = b + CNN(b) for b [n, H, W] (the activations are kept for backward)."""
+        buf = self._buffers(*b.shape)
+        return ops.cnn_forward(self.packed, b, buf["acts"], buf["u"])
+
+    def backward(self, b: torch.Tensor, du: torch.Tensor) -> torch.Tensor:
+        """Parameter gradient of <du, u> after forward(b)."""
+        buf = self._buffers(*b.shape)
+        return ops.cnn_backward(self.packed, b, buf["acts"], du, buf["dacts"], self.grad,
+                                buf["ws"])
+
+    def adam(self, lr: float) -> None:
+        self.step += 1
+        ops.adam_step(self.params, self.m, self.v, self.grad, self.step, lr)
+        self.pack()
+
+    # ------------------------------------------------------------ checkpoint
+    def save(self, path: str, meta: dict | None = None) -> None:
+        np.savez(path, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(),
+                 v=self.v.cpu().numpy(), step=np.int64(self.step),
+                 meta=np.array(json.dumps(meta or {})))
+
+    @classmethod
+    def load(cls, path: str, device="cuda:0") -> "WarmStartCNN":
+        z = np.load(path, allow_pickle=False)
+        net = cls(device, params=z["params"])
+        net.m.copy_(torch.from_numpy(z["m"]))
+        net.v.copy_(torch.from_numpy(z["v"]))
+        net.step = int(z["step"])
+        net.meta = json.loads(str(z["meta"]))
+        return net
+
+
+def warm_coefficients(net: WarmStartCNN, w: ops.WaveletSpec, b: torch.Tensor,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """c = W^dagger (b + CNN(b)) for b [n, H, W] -> [n, ncoef]."""
+    return ops.wavelet_analysis(w, net.forward(b), out=out)
+
+
+def warm_start(net: WarmStartCNN, w: ops.WaveletSpec, b: torch.Tensor, lam: float,
+               L: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """x_0 = soft(W^dagger (b + CNN(b)), lambda / L), [n, ncoef]."""
+    c = warm_coefficients(net, w, b, out=out)
+    return ops.soft_threshold(c, lam / L, out=c)
+
+
+def train_step(net: WarmStartCNN, w: ops.WaveletSpec, b: torch.Tensor, x_star: torch.Tensor,
+               lr: float, loss: torch.Tensor | None = None) -> torch.Tensor:
+    """One Adam step on mean (W^dagger u - x*)^2 over the batch; returns the
+    summed squared error (FP64 device scalar) before the step."""
+    n = b.shape[0]
+    c = warm_coefficients(net, w, b)
+    g = torch.empty_like(c)
+    loss = ops.sq_error(c, x_star, scale=1.0 / c.numel(), grad=g, loss=loss)
+    du = ops.wavelet_analysis_adjoint(w, g)
+    net.backward(b, du.view(n, w.rows, w.cols))
+    net.adam(lr)
+    return loss
+
+
+# --------------------------------------------------------------- problems
+def problem_batch(seed: int, start: int, count: int, rows: int, cols: int, device,
+                  noise: float = 1e-3):
+    """Images start..start+count-1 of stream `seed`: clean image from the
+    rectangle generator, sigma ~ U[1, 3], radius ceil(3 sigma),
+    b = R image + N(0, noise^2) (blur on the GPU)."""
+    from workloads import gen_image, gen_noise, gen_warm_problem, rng_for
+
+    bs, blurs = [], []
+    for i in range(start, start + count):
+        rng = rng_for(seed, i)
+        img = gen_image(rng, rows, cols)
+        sigma, radius = gen_warm_problem(rng)
+        bsp = ops.BlurSpec(rows, cols, sigma=sigma, radius=radius)
+        x = torch.tensor(img, dtype=torch.float32, device=device)
+        nz = torch.tensor(gen_noise(rng, (rows, cols), noise), dtype=torch.float32,
+                          device=device)
+        bs.append(ops.blur(bsp, x) + nz)
+        blurs.append(bsp)
+    return torch.stack(bs), blurs
+
+
+def fista_targets(w: ops.WaveletSpec, blurs, b: torch.Tensor, lam: float, iters: int,
+                  out: torch.Tensor) -> None:
+    """out[i] = x_iters of FISTA from zero on problem i (batched uneven plan)."""
+    bf = BatchedFista([(w, bsp) for bsp in blurs], list(b), lam)
+    bf.run(iters, graph=True)
+    out.copy_(bf.X.view(len(blurs), -1))
+
+
+def log(msg: str) -> None:
+    print(f"[warm-start {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def make_pairs(w: ops.WaveletSpec, n: int, lam: float, iters: int, seed: int, device,
+               chunk: int = 64):
+    """Training pairs (b [n, H, W], x* [n, ncoef]) resident on the device."""
+    B = torch.empty(n, w.rows, w.cols, dtype=torch.float32, device=device)
+    X = torch.empty(n, w.ncoef, dtype=torch.float32, device=device)
+    t0 = time.time()
+    for s in range(0, n, chunk):
+        c = min(chunk, n - s)
+        b, blurs = problem_batch(seed, s, c, w.rows, w.cols, device)
+        B[s:s + c].copy_(b)
+        fista_targets(w, blurs, b, lam, iters, X[s:s + c])
+        if (s // chunk) % 8 == 0:
+            torch.cuda.synchronize(device)
+            log(f"pairs {s + c}/{n} ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize(device)
+    return B, X
+
+
+def train(net: WarmStartCNN, w: ops.WaveletSpec, B: torch.Tensor, X: torch.Tensor,
+          epochs: int, batch: int, lr: float, lr_min: float, seed: int = 0):
+    """Adam over shuffled minibatches with a cosine learning-rate decay;
+    returns the mean training loss of each epoch."""
+    n = B.shape[0]
+    steps = epochs * (n // batch)
+    rng = np.random.default_rng((32, seed))
+    loss = torch.zeros(1, dtype=torch.float64, device=B.device)
+    hist = []
+    k = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(B.device)
+        acc = torch.zeros(1, dtype=torch.float64, device=B.device)
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * k / max(1, steps)))
+            train_step(net, w, B[idx].contiguous(), X[idx].contiguous(), cur, loss=loss)
+            acc += loss
+            k += 1
+        mean = acc.item() / ((n // batch) * batch * w.ncoef)
+        hist.append(mean)
+        log(f"epoch {ep + 1}/{epochs}: mean sq error {mean:.4e} ({time.time() - t0:.1f} s)")
+    return hist
+
+
+# -------------------------------------------------------------- evaluation
+def _objectives(w, blurs, b, X, lam, out):
+    for i, bsp in enumerate(blurs):
+        ops.objective(w, bsp, b[i], X[i], lam, out=out[i:i + 1])
+    return out
+
+
+def iterations_to_target(bf: BatchedFista, w, blurs, b, lam, F_star, x0, tol: float,
+                         max_iters: int):
+    """Run FISTA from x0 ([n, ncoef] or None for zero) one graph replay at a
+    time and return per-image first k with (F(x_k) - F*) / F* <= tol (exact
+    objectives), plus the lowest F seen per image."""
+    n = len(blurs)
+    bf.reset()
+    if x0 is not None:
+        bf.X.view(n, -1).copy_(x0)
+        bf.Y.copy_(bf.X)
+    obj = torch.empty(n, 3, dtype=torch.float64, device=b.device)
+    hit = [None] * n
+    F_min = [math.inf] * n
+    X = bf.X.view(n, -1)
+    for k in range(1, max_iters + 1):
+        bf.run(1, graph=True)
+        F = _objectives(w, blurs, b, X, lam, obj)[:, 2].cpu().numpy()
+        for i in range(n):
+            F_min[i] = min(F_min[i], F[i])
+            if hit[i] is None and (F[i] - F_star[i]) / F_star[i] <= tol:
+                hit[i] = k
+        if all(h is not None for h in hit):
+            break
+    return hit, F_min
+
+
+def choose_starts(w, blurs, b, x0: torch.Tensor, lam: float):
+    """The fallback rule per image: keep x_0 if finite with F(x_0) <= F(0)."""
+    n = len(blurs)
+    obj = _objectives(w, blurs, b, x0, lam, torch.empty(n, 3, dtype=torch.float64,
+                                                          device=b.device))
+    F0 = 0.5 * (b.double() ** 2).sum(dim=(1, 2))
+    ok = torch.isfinite(obj[:, 2]) & (obj[:, 2] <= F0)
+    x0 = torch.where(ok[:, None], x0, torch.zeros_like(x0))
+    return x0, ok
+
+
+def evaluate(net: WarmStartCNN, w: ops.WaveletSpec, n: int, lam: float, seed: int, device,
+             tol: float = 1e-4, star_iters: int = 4000, max_iters: int = 3000,
+             chunk: int = 64):
+    """Plain versus warm FISTA on n fresh images, chunk images per batched
+    plan: per-image iterations to (F - F*) / F* <= tol, and the wall time of
+    each batch until its slowest image gets there (warm includes the CNN, the
+    analysis, the threshold and the fallback check). F* is the lowest exact
+    objective over a star_iters-iteration plain run and both counted runs."""
+    res = {"plain_iters": [], "warm_iters": [], "plain_ms": [], "warm_ms": [],
+           "fallbacks": 0, "images": 0}
+    for s in range(0, n, chunk):
+        c = min(chunk, n - s)
+        b, blurs = problem_batch(seed, s, c, w.rows, w.cols, device)
+        bf = BatchedFista([(w, bsp) for bsp in blurs], list(b), lam)
+        bf.run(star_iters, graph=True)
+        obj = _objectives(w, blurs, b, bf.X.view(c, -1), lam,
+                          torch.empty(c, 3, dtype=torch.float64, device=device))
+        F_star = obj[:, 2].cpu().numpy()
+        # counting runs (exact objective after every iteration)
+        p_hit, p_min = iterations_to_target(bf, w, blurs, b, lam, F_star, None, tol, max_iters)
+        x0 = warm_start(net, w, b, lam)
+        x0, ok = choose_starts(w, blurs, b, x0, lam)
+        w_hit, w_min = iterations_to_target(bf, w, blurs, b, lam, F_star, x0, tol, max_iters)
+        low = np.minimum(p_min, w_min)
+        if np.any(low < F_star):
+            # a counted run went below F*: lower F* and count again
+            F_star = np.minimum(F_star, low)
+            p_hit, _ = iterations_to_target(bf, w, blurs, b, lam, F_star, None, tol, max_iters)
+            w_hit, _ = iterations_to_target(bf, w, blurs, b, lam, F_star, x0, tol, max_iters)
+        kp = max(h if h is not None else max_iters for h in p_hit)
+        kw = max(h if h is not None else max_iters for h in w_hit)
+        # timed runs: the batch until its slowest image reaches the target
+        torch.cuda.synchronize(device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        bf.reset()
+        e0.record()
+        bf.run(kp, graph=True)
+        e1.record()
+        torch.cuda.synchronize(device)
+        res["plain_ms"].append(e0.elapsed_time(e1))
+        bf.reset()
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        x0t = warm_start(net, w, b, lam)
+        x0t, _ = choose_starts(w, blurs, b, x0t, lam)
+        bf.X.view(c, -1).copy_(x0t)
+        bf.Y.copy_(bf.X)
+        bf.run(kw, graph=True)
+        torch.cuda.synchronize(device)
+        res["warm_ms"].append(1e3 * (time.perf_counter() - t0))
+        res["plain_iters"] += [h if h is not None else -1 for h in p_hit]
+        res["warm_iters"] += [h if h is not None else -1 for h in w_hit]
+        res["fallbacks"] += int((~ok).sum().item())
+        res["images"] += c
+        log(f"eval {s + c}/{n}: plain {kp} it {res['plain_ms'][-1]:.1f} ms, "
+            f"warm {kw} it {res['warm_ms'][-1]:.1f} ms")
+    return res
+
+
+def main(argv=None) -> int:
+    import argparse
+    import os
+
+    ap = argparse.ArgumentParser(description="train and evaluate the warm-start CNN")
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--fista-iters", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-min", type=float, default=2e-5)
+    ap.add_argument("--eval-images", type=int, default=1000)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", required=True, help="directory for the checkpoint and report")
+    a = ap.parse_args(argv)
+    dev = torch.device("cuda:0")
+    lam = 2e-5
+    w = ops.WaveletSpec(a.size, a.size, 4, taps=8, bc="sym")
+    os.makedirs(a.out, exist_ok=True)
+    t0 = time.time()
+    B, X = make_pairs(w, a.pairs, lam, a.fista_iters, seed=40 + a.seed, device=dev)
+    t_data = time.time() - t0
+    net = WarmStartCNN(dev, seed=a.seed)
+    t0 = time.time()
+    hist = train(net, w, B, X, a.epochs, a.batch, a.lr, a.lr_min, seed=a.seed)
+    t_train = time.time() - t0
+    del B, X
+    torch.cuda.empty_cache()
+    meta = {"pairs": a.pairs, "fista_iters": a.fista_iters, "epochs": a.epochs,
+            "batch": a.batch, "lr": a.lr, "lr_min": a.lr_min, "size": a.size, "lambda": lam,
+            "wavelet": "db4 J=4 sym", "seed": a.seed, "train_loss": hist,
+            "data_s": round(t_data, 1), "train_s": round(t_train, 1)}
+    net.save(os.path.join(a.out, f"warmstart_db4_J4_{a.size}.npz"), meta)
+    log("checkpoint written")
+    res = evaluate(net, w, a.eval_images, lam, seed=50 + a.seed, device=dev)
+    meta["eval"] = summarize(res)
+    with open(os.path.join(a.out, "report.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    log(json.dumps(meta["eval"]))
+    return 0
+
+
+def summarize(res: dict) -> dict:
+    p = np.array(res["plain_iters"], dtype=float)
+    q = np.array(res["warm_iters"], dtype=float)
+    return {"images": res["images"], "fallbacks": res["fallbacks"],
+            "plain_iters_mean": float(p.mean()), "warm_iters_mean": float(q.mean()),
+            "plain_iters_median": float(np.median(p)), "warm_iters_median": float(np.median(q)),
+            "warm_fewer_iters_frac": float(np.mean(q < p)),
+            "plain_batch_ms_mean": float(np.mean(res["plain_ms"])),
+            "warm_batch_ms_mean": float(np.mean(res["warm_ms"])),
+            "unreached_plain": int(np.sum(p < 0)), "unreached_warm": int(np.sum(q < 0))}
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

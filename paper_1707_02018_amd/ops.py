@@ -317,3 +317,108 @@ def conv_adjoint_pair(h: torch.Tensor, s: torch.Tensor, x_obs: torch.Tensor | No
         _dtype_code(h), B, K, N, _ptr(h), _ptr(s), _ptr(_dev(x_obs)) if x_obs is not None else None,
         _ptr(resid), _ptr(gh), _ptr(gs), _stream(h)))
     return resid, gh, gs
+
+
+# ------------------------------------------------------- warm-start CNN
+CNN_PARAMS = 37601
+CNN_CHANNELS = 32
+
+
+def cnn_sizes(batch: int, rows: int, cols: int):
+    """(packed parameter bytes, activation bytes, backward workspace bytes)."""
+    pk, act, ws = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    check("aw_cnn_sizes", load().aw_cnn_sizes(batch, rows, cols, ctypes.byref(pk),
+                                              ctypes.byref(act), ctypes.byref(ws)))
+    return int(pk.value), int(act.value), int(ws.value)
+
+
+def _f32(t: torch.Tensor) -> torch.Tensor:
+    _dev(t)
+    if t.dtype != torch.float32:
+        raise ValueError("float32 tensors expected")
+    return t
+
+
+def cnn_pack(params: torch.Tensor, packed: torch.Tensor) -> torch.Tensor:
+    """BF16 kernel layouts of the FP32 master parameters (device-side)."""
+    _f32(params)
+    if params.numel() != CNN_PARAMS:
+        raise ValueError(f"{CNN_PARAMS} parameters expected")
+    check("aw_cnn_pack", load().aw_cnn_pack(_ptr(params), _ptr(_dev(packed)), _stream(params)))
+    return packed
+
+
+def _img_batch(b: torch.Tensor):
+    if b.dim() == 2:
+        return 1, b.shape[0], b.shape[1]
+    if b.dim() != 3:
+        raise ValueError("images [rows, cols] or [batch, rows, cols] expected")
+    return b.shape[0], b.shape[1], b.shape[2]
+
+
+def cnn_forward(packed: torch.Tensor, b: torch.Tensor, acts: torch.Tensor,
+                u: torch.Tensor | None = None) -> torch.Tensor:
+    """u = b + CNN(b); acts (uint8 buffer of cnn_sizes()[1] bytes) receives y_1..y_5."""
+    _f32(b)
+    n, H, W = _img_batch(b)
+    if u is None:
+        u = torch.empty_like(b)
+    check("aw_cnn_forward", load().aw_cnn_forward(_ptr(_dev(packed)), n, H, W, _ptr(b),
+                                                  _ptr(_dev(acts)), _ptr(_f32(u)), _stream(b)))
+    return u
+
+
+def cnn_backward(packed: torch.Tensor, b: torch.Tensor, acts: torch.Tensor, du: torch.Tensor,
+                 dacts: torch.Tensor, grad: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+    """grad = d<du, CNN(b)>/d params (FP32 master layout, overwritten)."""
+    _f32(b)
+    n, H, W = _img_batch(b)
+    if du.shape != b.shape:
+        raise ValueError("du must have the shape of b")
+    check("aw_cnn_backward", load().aw_cnn_backward(
+        _ptr(_dev(packed)), n, H, W, _ptr(b), _ptr(_dev(acts)), _ptr(_f32(du)),
+        _ptr(_dev(dacts)), _ptr(_f32(grad)), _ptr(_dev(ws)), ws.numel() * ws.element_size(),
+        _stream(b)))
+    return grad
+
+
+def adam_step(params, m, v, grad, step: int, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8) -> None:
+    n = params.numel()
+    for t in (params, m, v, grad):
+        _f32(t)
+        if t.numel() != n:
+            raise ValueError("params, m, v and grad must have the same size")
+    check("aw_adam_step", load().aw_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), n, step,
+                                              lr, beta1, beta2, eps, _stream(params)))
+
+
+def sq_error(c: torch.Tensor, target: torch.Tensor, scale: float = 1.0,
+             grad: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+    """loss = sum (c - target)^2 (FP64 device scalar); grad = scale * 2 (c - target)."""
+    _f32(c)
+    _f32(target)
+    n = c.numel()
+    if target.numel() != n or (grad is not None and grad.numel() != n):
+        raise ValueError("size mismatch")
+    need = ctypes.c_size_t()
+    check("aw_sq_error_workspace", load().aw_sq_error_workspace(n, ctypes.byref(need)))
+    if ws is None:
+        ws = torch.empty(need.value, dtype=torch.uint8, device=c.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=c.device)
+    check("aw_sq_error", load().aw_sq_error(n, _ptr(c), _ptr(target), scale,
+                                            _ptr(_f32(grad)) if grad is not None else None,
+                                            _ptr(_dev(loss)), _ptr(_dev(ws)),
+                                            ws.numel() * ws.element_size(), _stream(c)))
+    return loss
+
+
+def soft_threshold(x: torch.Tensor, tau: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    _f32(x)
+    if out is None:
+        out = torch.empty_like(x)
+    check("aw_soft_threshold", load().aw_soft_threshold(x.numel(), _ptr(x), tau, _ptr(_f32(out)),
+                                                        _stream(x)))
+    return out

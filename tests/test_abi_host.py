@@ -164,3 +164,29 @@ def test_batch_plan_validates_before_device_work(lib):
     b2[0].rows, b2[0].cols, b2[0].radius = 5, 9, 0
     b2[0].taps[0] = 1.0
     assert lib.aw_batch_create(1, w2, b2, ctypes.byref(plan)) == _lib.EUNSUPPORTED
+
+
+def test_cnn_entry_points_validate(lib):
+    pk, act, ws = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.aw_cnn_sizes(4, 512, 512, ctypes.byref(pk), ctypes.byref(act),
+                            ctypes.byref(ws)) == _lib.OK
+    assert act.value == 4 * 512 * 512 * 5 * 32 * 2
+    # packed: BF16 forward + mirrored copies of four mid layers, output layer padded to 32
+    assert pk.value == 9 * 32 * 2 + 128 + 4 * (2 * 9216 * 2 + 128) + 9216 * 2 + 128 + 9 * 32 * 2
+    assert ws.value >= 9248 * 4
+    assert lib.aw_cnn_sizes(0, 8, 8, None, None, None) == _lib.EINVAL
+    assert lib.aw_cnn_sizes(64, 4096, 4096, None, None, None) == _lib.EINVAL  # index range
+    d = ctypes.c_void_p(0x1000)
+    assert lib.aw_cnn_pack(None, d, None) == _lib.EINVAL
+    assert lib.aw_cnn_forward(d, 1, 8, 8, d, d, d, None) == _lib.EINVAL       # u aliases b
+    assert lib.aw_cnn_forward(d, 1, 0, 8, d, d, ctypes.c_void_p(0x2000), None) == _lib.EINVAL
+    e = ctypes.c_void_p(0x2000)
+    assert lib.aw_cnn_backward(d, 1, 8, 8, d, d, d, e, d, d, 16, None) == _lib.EINVAL  # ws
+    assert lib.aw_cnn_backward(d, 1, 8, 8, d, d, d, d, d, d, 1 << 30, None) == _lib.EINVAL
+    assert lib.aw_adam_step(d, d, d, d, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.EINVAL
+    assert lib.aw_adam_step(d, d, d, d, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == _lib.EINVAL
+    assert lib.aw_adam_step(d, d, d, d, 10, 1, -1.0, 0.9, 0.999, 1e-8, None) == _lib.EINVAL
+    assert lib.aw_soft_threshold(10, d, -1.0, d, None) == _lib.EINVAL
+    assert lib.aw_sq_error(10, d, d, 1.0, None, d, d, 0, None) == _lib.EINVAL  # ws too small
+    n = ctypes.c_size_t()
+    assert lib.aw_sq_error_workspace(100000, ctypes.byref(n)) == _lib.OK and n.value >= 8

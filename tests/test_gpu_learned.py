@@ -1,0 +1,116 @@
+"""Learned warm start on the GPU: the warm map and the training gradient
+against the FP64 oracle, a short training run that lowers the loss, the
+fallback rule, and (with the committed checkpoint) fewer FISTA iterations to
+the 1e-4 relative objective than the zero start on fresh images."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+from oracle import filters as ofl
+from oracle import fista as ofi
+from oracle import wavelet as owv
+from paper_1707_02018_amd import learned, ops
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LAM = 2e-5
+CKPT = os.path.join(os.path.dirname(learned.__file__), "weights", "warmstart_db4_J4_512.npz")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+
+
+def test_warm_map_composes_with_oracle_analysis():
+    w = ops.WaveletSpec(40, 56, 2, taps=8, bc="sym")
+    b, _ = learned.problem_batch(60, 0, 3, 40, 56, DEV)
+    net = learned.WarmStartCNN(DEV, seed=1)
+    u = net.forward(b).clone()
+    x0 = learned.warm_start(net, w, b, LAM)
+    torch.cuda.synchronize()
+    h = ofl.by_taps(8)
+    for i in range(3):
+        ref = ofi.soft(owv.W_pinv(u[i].double().cpu().numpy(), h, "sym", 2), LAM)
+        got = x0[i].double().cpu().numpy()
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    # the whole map against the unrounded FP64 network (BF16 tolerance)
+    th = learned.init_params(1)
+    ref = cnn.warm_start(th, b[0].double().cpu().numpy(), h, "sym", 2, LAM)
+    got = x0[0].double().cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 2e-2 * np.linalg.norm(ref)
+
+
+def test_training_gradient_matches_oracle():
+    """The gradient of one training step against the FP64 oracle's loss
+    gradient (differences come from BF16 activations: a direction check plus a
+    loose magnitude check)."""
+    w = ops.WaveletSpec(32, 48, 2, taps=8, bc="sym")
+    b, _ = learned.problem_batch(61, 0, 2, 32, 48, DEV)
+    rng = np.random.default_rng(3)
+    xs = torch.tensor(rng.standard_normal((2, w.ncoef)) * 0.1, dtype=torch.float32, device=DEV)
+    net = learned.WarmStartCNN(DEV, params=learned.init_params(2, out_scale=1.0))
+    c = learned.warm_coefficients(net, w, b)
+    g = torch.empty_like(c)
+    loss = ops.sq_error(c, xs, scale=1.0, grad=g)
+    du = ops.wavelet_analysis_adjoint(w, g)
+    grad = net.backward(b, du).double().cpu().numpy()
+    torch.cuda.synchronize()
+    h = ofl.by_taps(8)
+    th = learned.init_params(2, out_scale=1.0)
+    tot, gref = 0.0, np.zeros_like(th)
+    for i in range(2):
+        l, gi = cnn.loss_and_grad(th, b[i].double().cpu().numpy(), xs[i].double().cpu().numpy(),
+                                  h, "sym", 2)
+        tot += l
+        gref += gi
+    assert abs(loss.item() - tot) <= 2e-2 * tot
+    cos = float(grad @ gref) / (np.linalg.norm(grad) * np.linalg.norm(gref))
+    assert cos >= 0.99, cos
+    assert abs(np.linalg.norm(grad) / np.linalg.norm(gref) - 1.0) <= 0.05
+
+
+def test_short_training_lowers_the_loss():
+    w = ops.WaveletSpec(64, 64, 3, taps=8, bc="sym")
+    B, X = learned.make_pairs(w, 32, LAM, 150, seed=62, device=DEV, chunk=16)
+    # reference: no network at all (u = b, x_0 = W^dagger b)
+    base = ops.sq_error(ops.wavelet_analysis(w, B), X).item() / X.numel()
+    net = learned.WarmStartCNN(DEV, seed=3)
+    hist = learned.train(net, w, B, X, epochs=12, batch=8, lr=2e-3, lr_min=2e-4)
+    assert all(np.isfinite(hist))
+    assert all(b <= a * 1.02 for a, b in zip(hist, hist[1:])), hist
+    c = learned.warm_coefficients(net, w, B)
+    after = ops.sq_error(c, X).item() / X.numel()
+    assert after < 0.85 * base, (after, base, hist)
+
+
+def test_fallback_rule_rejects_bad_starts():
+    w = ops.WaveletSpec(40, 56, 2, taps=8, bc="sym")
+    b, blurs = learned.problem_batch(63, 0, 3, 40, 56, DEV)
+    x0 = torch.zeros(3, w.ncoef, dtype=torch.float32, device=DEV)
+    x0[0] = float("nan")
+    x0[1] = 100.0
+    x0[2] = ops.wavelet_analysis(w, b[2])
+    out, ok = learned.choose_starts(w, blurs, b, x0, LAM)
+    torch.cuda.synchronize()
+    assert ok.tolist() == [False, False, True]
+    assert torch.equal(out[0], torch.zeros_like(out[0]))
+    assert torch.equal(out[1], torch.zeros_like(out[1]))
+    assert torch.equal(out[2], x0[2])
+
+
+@pytest.mark.skipif(not os.path.exists(CKPT), reason="no trained checkpoint")
+def test_trained_network_needs_fewer_iterations():
+    """What the trained network gains over the zero start: fresh 512 x 512
+    images (an evaluation stream the training never saw)."""
+    net = learned.WarmStartCNN.load(CKPT, DEV)
+    w = ops.WaveletSpec(512, 512, 4, taps=8, bc="sym")
+    res = learned.evaluate(net, w, 8, LAM, seed=70, device=DEV, star_iters=3000,
+                           max_iters=2000, chunk=8)
+    s = learned.summarize(res)
+    assert s["unreached_plain"] == 0 and s["unreached_warm"] == 0, s
+    assert s["warm_iters_mean"] < s["plain_iters_mean"], s
