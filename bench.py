@@ -119,6 +119,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, autograd and convolution-pair sections")
     ap.add_argument("--batched-iters", type=int, default=300)
+    ap.add_argument("--warm-images", type=int, default=16)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print traffic records from two rocprofv3 --pmc counter CSVs "
                          "(FETCH_SIZE, WRITE_SIZE) of a --copy-reference run, then exit")
@@ -221,6 +222,39 @@ def bench_conv(torch, ops) -> dict:
     return {"pairs": B, "K": K, "N": N, "ms": round(ms, 3),
             "GFLOPs": round(flops / (ms * 1e-3) / 1e9, 1),
             "frac_fp32_vector_peak_157T": round(flops / (ms * 1e-3) / 157.3e12, 4)}
+
+
+def bench_warm(torch, ops, n_images: int) -> dict:
+    """Learned warm start against FISTA from zero on fresh 512^2 images
+    (db4, J = 4, sym, PSF sigma ~ U[1, 3], lambda = 2e-5) with the committed
+    checkpoint: iterations to the 1e-4 relative objective per image and the
+    batch wall time until its slowest image gets there."""
+    from paper_1707_02018_amd import learned
+
+    ckpt = os.path.join(ROOT, "paper_1707_02018_amd", "weights", "warmstart_db4_J4_512.npz")
+    if not os.path.exists(ckpt):
+        return {"skipped": "no checkpoint"}
+    dev = torch.device("cuda:0")
+    net = learned.WarmStartCNN.load(ckpt, dev)
+    w = ops.WaveletSpec(512, 512, 4, taps=8, bc="sym")
+    # CNN inference alone at the evaluation batch
+    b, _ = learned.problem_batch(72, 0, n_images, 512, 512, dev)
+    net.forward(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        learned.warm_start(net, w, b, 2e-5)
+    torch.cuda.synchronize()
+    cnn_ms = 1e3 * (time.perf_counter() - t0) / 10
+    res = learned.evaluate(net, w, n_images, 2e-5, seed=72, device=dev, star_iters=16000,
+                           max_iters=12000, every=40, chunk=n_images)
+    s = learned.summarize(res)
+    s["warm_start_map_ms"] = round(cnn_ms, 3)
+    s["cnn_gflop_per_image"] = round(2 * 37440 * 512 * 512 / 1e9, 2)
+    s["cnn_tflops"] = round(2 * 37440 * 512 * 512 * n_images / (cnn_ms * 1e-3) / 1e12, 1)
+    s["training"] = {k: net.meta[k] for k in ("pairs", "fista_iters", "epochs", "batch")}
+    s["training_eval"] = net.meta.get("eval")
+    return s
 
 
 def cpu_baseline(size: int, bc: str, iters: int = 2) -> dict:
@@ -370,10 +404,11 @@ def main():
     # ------------------------------------------------ time to 1e-4 (plain)
     target = None
     if not args.no_target:
+        log("time to 1e-4 (2048^2, plain)")
         st2 = ops.FistaState(w, bsp, b)
         obj = torch.empty(1, 3, dtype=torch.float64, device=dev)
         Fs = []
-        every, total = 5, 3000
+        every, total = 20, 20000
         for k in range(1, total + 1):
             ops.fista_step(st2, b, lam)
             if k % every == 0:
@@ -397,6 +432,9 @@ def main():
         torch.cuda.empty_cache()
         log("convolution pair")
         extras["conv_adjoint_pair"] = bench_conv(torch, ops)
+        torch.cuda.empty_cache()
+        log("warm start (512^2)")
+        extras["warm_start"] = bench_warm(torch, ops, args.warm_images)
     log("cpu baseline")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(N, args.bc)

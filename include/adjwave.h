@@ -277,9 +277,9 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
  *             as weight [out][in][3][3] then bias [out].
  * Precision   Weights and activations are rounded to BF16 (nearest even);
  *             products accumulate in FP32 (v_mfma_f32_32x32x16_bf16 for the
- *             32-channel layers). The input image and the incoming gradient
- *             are rounded to BF16 where they enter a convolution; biases stay
- *             FP32.
+ *             32-channel layers). The input image enters the first layer in
+ *             FP32; the incoming gradient du is rounded to BF16 where it
+ *             enters a convolution; biases stay FP32.
  * Activations [5][batch][rows][cols][32] BF16 (uint16 bit patterns), the
  *             outputs y_1..y_5 of layers 1..5 after ReLU (AW_CNN_ACT_BYTES per
  *             pixel). Gradients at the pre-activations of layers 1..5 use the

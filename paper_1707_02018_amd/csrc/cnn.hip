@@ -108,8 +108,10 @@ __global__ void cnn_pack_kernel(const float* __restrict__ m, uint8_t* __restrict
 constexpr int kPackJobs = 288 + 32 + 4 * (2 * 9216 + 32) + 9216 + 32 + 288;
 
 // ------------------------------------------------------- 1 -> 32 (VALU)
-// y[p][c] = sum_t w[t][c] rnd(src[p + off(t)])   (+ bias, ReLU)   or   (* [mask > 0])
+// FWD:  y[p][c] = relu(bias[c] + sum_t w[t][c] src[p + off(t)])   (src = the FP32 image)
+// else: y[p][c] = [mask[p][c] > 0] sum_t w[t][c] rnd(src[p + off(t)])   (src = a gradient)
 // One thread per (pixel, group of 8 channels); off(t) = (t / 3 - 1, t % 3 - 1).
+// The image keeps FP32: its noise (1e-3) is below the BF16 step near 1 (2^-8).
 template <bool FWD>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ src,
                                                       const uint16_t* __restrict__ w,
@@ -129,7 +131,8 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
-    in[t] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? rnd_bf(s[(long long)rr * W + cc]) : 0.0f;
+    const float v = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
+    in[t] = FWD ? v : rnd_bf(v);
   }
   float acc[8];
 #pragma unroll
@@ -468,7 +471,8 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
 }
 
 // ------------------------------ 1-channel weight gradients (VALU)
-// out[c][t] = sum_p X32[p][c] rnd(x1[p + off(t)]) (stored at c * 9 + (flip ? 8 - t : t)),
+// out[c][t] = sum_p X32[p][c] x1'[p + off(t)] (stored at c * 9 + (flip ? 8 - t : t)),
+// x1' = x1 for the input layer (the FP32 image), rnd(x1) for the output layer (a gradient);
 // out[288 + c] = sum_p X32[p][c] (width 320)  or  out[288] = sum_p x1[p] (width 289).
 constexpr int kWinPix = 4096;  // pixels per workgroup
 
@@ -494,7 +498,8 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
-      in[t] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? rnd_bf(s[(long long)rr * W + cc]) : 0.0f;
+      const float v = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
+      in[t] = flip ? rnd_bf(v) : v;
     }
     const u32x4 v = ld16(X32 + p * 32 + 8 * g);
     float xv[8];

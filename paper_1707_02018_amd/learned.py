@@ -134,25 +134,39 @@ def train_step(net: WarmStartCNN, w: ops.WaveletSpec, b: torch.Tensor, x_star: t
 
 
 # --------------------------------------------------------------- problems
-def problem_batch(seed: int, start: int, count: int, rows: int, cols: int, device,
-                  noise: float = 1e-3):
-    """Images start..start+count-1 of stream `seed`: clean image from the
-    rectangle generator, sigma ~ U[1, 3], radius ceil(3 sigma),
-    b = R image + N(0, noise^2) (blur on the GPU)."""
+def problem_host(seed: int, start: int, count: int, rows: int, cols: int,
+                 noise: float = 1e-3):
+    """Host side of images start..start+count-1 of stream `seed`: clean image
+    from the rectangle generator, sigma ~ U[1, 3], radius ceil(3 sigma), and
+    the noise draw."""
     from workloads import gen_image, gen_noise, gen_warm_problem, rng_for
 
-    bs, blurs = [], []
+    out = []
     for i in range(start, start + count):
         rng = rng_for(seed, i)
         img = gen_image(rng, rows, cols)
         sigma, radius = gen_warm_problem(rng)
+        out.append((img, sigma, radius, gen_noise(rng, (rows, cols), noise)))
+    return out
+
+
+def problem_upload(host, rows: int, cols: int, device):
+    """b = R image + noise on the GPU for each host item; returns (b [n, H, W],
+    blur specs)."""
+    bs, blurs = [], []
+    for img, sigma, radius, nz in host:
         bsp = ops.BlurSpec(rows, cols, sigma=sigma, radius=radius)
         x = torch.tensor(img, dtype=torch.float32, device=device)
-        nz = torch.tensor(gen_noise(rng, (rows, cols), noise), dtype=torch.float32,
-                          device=device)
-        bs.append(ops.blur(bsp, x) + nz)
+        bs.append(ops.blur(bsp, x) + torch.tensor(nz, dtype=torch.float32, device=device))
         blurs.append(bsp)
     return torch.stack(bs), blurs
+
+
+def problem_batch(seed: int, start: int, count: int, rows: int, cols: int, device,
+                  noise: float = 1e-3):
+    """Images start..start+count-1 of stream `seed` as (b [n, H, W], blur specs)."""
+    return problem_upload(problem_host(seed, start, count, rows, cols, noise), rows, cols,
+                          device)
 
 
 def fista_targets(w: ops.WaveletSpec, blurs, b: torch.Tensor, lam: float, iters: int,
@@ -173,11 +187,15 @@ def make_pairs(w: ops.WaveletSpec, n: int, lam: float, iters: int, seed: int, de
     B = torch.empty(n, w.rows, w.cols, dtype=torch.float32, device=device)
     X = torch.empty(n, w.ncoef, dtype=torch.float32, device=device)
     t0 = time.time()
+    host = problem_host(seed, 0, min(chunk, n), w.rows, w.cols)
     for s in range(0, n, chunk):
         c = min(chunk, n - s)
-        b, blurs = problem_batch(seed, s, c, w.rows, w.cols, device)
+        b, blurs = problem_upload(host, w.rows, w.cols, device)
         B[s:s + c].copy_(b)
         fista_targets(w, blurs, b, lam, iters, X[s:s + c])
+        # the next chunk's images are drawn on the host while the GPU iterates
+        if s + c < n:
+            host = problem_host(seed, s + c, min(chunk, n - s - c), w.rows, w.cols)
         if (s // chunk) % 8 == 0:
             torch.cuda.synchronize(device)
             log(f"pairs {s + c}/{n} ({time.time() - t0:.1f} s)")
@@ -218,30 +236,30 @@ def _objectives(w, blurs, b, X, lam, out):
     return out
 
 
-def iterations_to_target(bf: BatchedFista, w, blurs, b, lam, F_star, x0, tol: float,
-                         max_iters: int):
-    """Run FISTA from x0 ([n, ncoef] or None for zero) one graph replay at a
-    time and return per-image first k with (F(x_k) - F*) / F* <= tol (exact
-    objectives), plus the lowest F seen per image."""
+def objective_curve(bf: BatchedFista, w, blurs, b, lam, x0, iters: int, every: int):
+    """FISTA from x0 ([n, ncoef], or None for zero) for `iters` iterations,
+    graph-replayed `every` at a time; returns the exact objectives F(x_k) at
+    k = every, 2 every, ... as an array [iters // every, n]."""
     n = len(blurs)
     bf.reset()
     if x0 is not None:
         bf.X.view(n, -1).copy_(x0)
         bf.Y.copy_(bf.X)
     obj = torch.empty(n, 3, dtype=torch.float64, device=b.device)
-    hit = [None] * n
-    F_min = [math.inf] * n
     X = bf.X.view(n, -1)
-    for k in range(1, max_iters + 1):
-        bf.run(1, graph=True)
-        F = _objectives(w, blurs, b, X, lam, obj)[:, 2].cpu().numpy()
-        for i in range(n):
-            F_min[i] = min(F_min[i], F[i])
-            if hit[i] is None and (F[i] - F_star[i]) / F_star[i] <= tol:
-                hit[i] = k
-        if all(h is not None for h in hit):
-            break
-    return hit, F_min
+    out = []
+    for _ in range(iters // every):
+        bf.run(every, graph=True)
+        out.append(_objectives(w, blurs, b, X, lam, obj)[:, 2].cpu().numpy().copy())
+    return np.array(out)
+
+
+def first_hits(curve: np.ndarray, F_star: np.ndarray, tol: float, every: int):
+    """Per image, the first checked k with (F(x_k) - F*) / F* <= tol (-1: never)."""
+    rel = (curve - F_star[None, :]) / F_star[None, :]
+    ok = rel <= tol
+    return [int(every * (np.argmax(ok[:, i]) + 1)) if ok[:, i].any() else -1
+            for i in range(curve.shape[1])]
 
 
 def choose_starts(w, blurs, b, x0: torch.Tensor, lam: float):
@@ -256,61 +274,53 @@ def choose_starts(w, blurs, b, x0: torch.Tensor, lam: float):
 
 
 def evaluate(net: WarmStartCNN, w: ops.WaveletSpec, n: int, lam: float, seed: int, device,
-             tol: float = 1e-4, star_iters: int = 4000, max_iters: int = 3000,
-             chunk: int = 64):
-    """Plain versus warm FISTA on n fresh images, chunk images per batched
-    plan: per-image iterations to (F - F*) / F* <= tol, and the wall time of
-    each batch until its slowest image gets there (warm includes the CNN, the
-    analysis, the threshold and the fallback check). F* is the lowest exact
-    objective over a star_iters-iteration plain run and both counted runs."""
+             tol: float = 1e-4, star_iters: int = 20000, max_iters: int = 16000,
+             every: int = 20, chunk: int = 64):
+    """Plain versus warm FISTA on n fresh images, `chunk` images per batched
+    plan. Counts: per image, the first k (checked every `every` iterations)
+    with (F(x_k) - F*) / F* <= tol, from exact objectives; F* is the lowest
+    exact objective seen over a star_iters-iteration plain run and both
+    counted runs. Times: the wall time of each batch until its slowest image
+    reaches the target (warm includes the CNN, the analysis, the threshold
+    and the fallback check)."""
     res = {"plain_iters": [], "warm_iters": [], "plain_ms": [], "warm_ms": [],
-           "fallbacks": 0, "images": 0}
+           "fallbacks": 0, "images": 0, "every": every, "tol": tol,
+           "star_iters": star_iters, "max_iters": max_iters}
     for s in range(0, n, chunk):
         c = min(chunk, n - s)
         b, blurs = problem_batch(seed, s, c, w.rows, w.cols, device)
         bf = BatchedFista([(w, bsp) for bsp in blurs], list(b), lam)
-        bf.run(star_iters, graph=True)
-        obj = _objectives(w, blurs, b, bf.X.view(c, -1), lam,
-                          torch.empty(c, 3, dtype=torch.float64, device=device))
-        F_star = obj[:, 2].cpu().numpy()
-        # counting runs (exact objective after every iteration)
-        p_hit, p_min = iterations_to_target(bf, w, blurs, b, lam, F_star, None, tol, max_iters)
-        x0 = warm_start(net, w, b, lam)
-        x0, ok = choose_starts(w, blurs, b, x0, lam)
-        w_hit, w_min = iterations_to_target(bf, w, blurs, b, lam, F_star, x0, tol, max_iters)
-        low = np.minimum(p_min, w_min)
-        if np.any(low < F_star):
-            # a counted run went below F*: lower F* and count again
-            F_star = np.minimum(F_star, low)
-            p_hit, _ = iterations_to_target(bf, w, blurs, b, lam, F_star, None, tol, max_iters)
-            w_hit, _ = iterations_to_target(bf, w, blurs, b, lam, F_star, x0, tol, max_iters)
-        kp = max(h if h is not None else max_iters for h in p_hit)
-        kw = max(h if h is not None else max_iters for h in w_hit)
-        # timed runs: the batch until its slowest image reaches the target
-        torch.cuda.synchronize(device)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        bf.reset()
-        e0.record()
-        bf.run(kp, graph=True)
-        e1.record()
-        torch.cuda.synchronize(device)
-        res["plain_ms"].append(e0.elapsed_time(e1))
+        star = objective_curve(bf, w, blurs, b, lam, None, star_iters, 1000)
+        plain = objective_curve(bf, w, blurs, b, lam, None, max_iters, every)
+        x0, ok = choose_starts(w, blurs, b, warm_start(net, w, b, lam), lam)
+        warm = objective_curve(bf, w, blurs, b, lam, x0, max_iters, every)
+        F_star = np.minimum(star.min(axis=0), np.minimum(plain.min(axis=0), warm.min(axis=0)))
+        p_hit = first_hits(plain, F_star, tol, every)
+        w_hit = first_hits(warm, F_star, tol, every)
+        kp = max(h if h > 0 else max_iters for h in p_hit)
+        kw = max(h if h > 0 else max_iters for h in w_hit)
         bf.reset()
         torch.cuda.synchronize(device)
         t0 = time.perf_counter()
-        x0t = warm_start(net, w, b, lam)
-        x0t, _ = choose_starts(w, blurs, b, x0t, lam)
+        bf.run(kp, graph=True)
+        torch.cuda.synchronize(device)
+        res["plain_ms"].append(1e3 * (time.perf_counter() - t0))
+        bf.reset()
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        x0t, _ = choose_starts(w, blurs, b, warm_start(net, w, b, lam), lam)
         bf.X.view(c, -1).copy_(x0t)
         bf.Y.copy_(bf.X)
         bf.run(kw, graph=True)
         torch.cuda.synchronize(device)
         res["warm_ms"].append(1e3 * (time.perf_counter() - t0))
-        res["plain_iters"] += [h if h is not None else -1 for h in p_hit]
-        res["warm_iters"] += [h if h is not None else -1 for h in w_hit]
+        res["plain_iters"] += p_hit
+        res["warm_iters"] += w_hit
         res["fallbacks"] += int((~ok).sum().item())
         res["images"] += c
-        log(f"eval {s + c}/{n}: plain {kp} it {res['plain_ms'][-1]:.1f} ms, "
-            f"warm {kw} it {res['warm_ms'][-1]:.1f} ms")
+        log(f"eval {s + c}/{n}: plain mean {np.mean(p_hit):.0f} it (batch {kp} it, "
+            f"{res['plain_ms'][-1]:.1f} ms), warm mean {np.mean(w_hit):.0f} it (batch {kw} it, "
+            f"{res['warm_ms'][-1]:.1f} ms)")
     return res
 
 
@@ -328,6 +338,9 @@ def main(argv=None) -> int:
     ap.add_argument("--eval-images", type=int, default=1000)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--star-iters", type=int, default=20000)
+    ap.add_argument("--max-iters", type=int, default=16000)
+    ap.add_argument("--every", type=int, default=20)
     ap.add_argument("--out", required=True, help="directory for the checkpoint and report")
     a = ap.parse_args(argv)
     dev = torch.device("cuda:0")
@@ -349,8 +362,11 @@ def main(argv=None) -> int:
             "data_s": round(t_data, 1), "train_s": round(t_train, 1)}
     net.save(os.path.join(a.out, f"warmstart_db4_J4_{a.size}.npz"), meta)
     log("checkpoint written")
-    res = evaluate(net, w, a.eval_images, lam, seed=50 + a.seed, device=dev)
+    res = evaluate(net, w, a.eval_images, lam, seed=50 + a.seed, device=dev,
+                   star_iters=a.star_iters, max_iters=a.max_iters, every=a.every)
     meta["eval"] = summarize(res)
+    meta["eval_per_image"] = {"plain_iters": res["plain_iters"], "warm_iters": res["warm_iters"],
+                              "plain_batch_ms": res["plain_ms"], "warm_batch_ms": res["warm_ms"]}
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(meta, f, indent=1)
     log(json.dumps(meta["eval"]))
@@ -360,10 +376,15 @@ def main(argv=None) -> int:
 def summarize(res: dict) -> dict:
     p = np.array(res["plain_iters"], dtype=float)
     q = np.array(res["warm_iters"], dtype=float)
-    return {"images": res["images"], "fallbacks": res["fallbacks"],
-            "plain_iters_mean": float(p.mean()), "warm_iters_mean": float(q.mean()),
-            "plain_iters_median": float(np.median(p)), "warm_iters_median": float(np.median(q)),
-            "warm_fewer_iters_frac": float(np.mean(q < p)),
+    both = (p > 0) & (q > 0)
+    return {"images": res["images"], "fallbacks": res["fallbacks"], "tol": res["tol"],
+            "checked_every": res["every"], "star_iters": res["star_iters"],
+            "max_iters": res["max_iters"], "reached_both": int(both.sum()),
+            "plain_iters_mean": float(p[both].mean()) if both.any() else None,
+            "warm_iters_mean": float(q[both].mean()) if both.any() else None,
+            "plain_iters_median": float(np.median(p[both])) if both.any() else None,
+            "warm_iters_median": float(np.median(q[both])) if both.any() else None,
+            "warm_fewer_iters_frac": float(np.mean(q[both] < p[both])) if both.any() else None,
             "plain_batch_ms_mean": float(np.mean(res["plain_ms"])),
             "warm_batch_ms_mean": float(np.mean(res["warm_ms"])),
             "unreached_plain": int(np.sum(p < 0)), "unreached_warm": int(np.sum(q < 0))}

@@ -1,7 +1,7 @@
 """Warm-start CNN kernels (BF16 operands, FP32 accumulation) against the FP64
 oracle, layer by layer: each GPU layer is compared with the oracle applied to
-the GPU's own BF16 inputs and BF16-rounded weights, so the check isolates one
-kernel at a time.
+the GPU's own BF16 inputs (the FP32 image for the first layer) and BF16-rounded
+weights, so the check isolates one kernel at a time.
 
 Tolerances (derived from the arithmetic): a BF16-stored output is within
 2^-8 |z| of the exact value z (round to nearest) plus the FP32 accumulation
@@ -107,7 +107,7 @@ def test_forward_layers_match_oracle(shape):
     u = u.double().cpu().numpy()
     b32 = imgs.astype(np.float32).astype(np.float64)
     for i in range(n):
-        x = bf16(b32[i])[None]
+        x = b32[i][None]  # the image enters in FP32
         for k in range(5):
             z, S = layer_ref(k, thk, x)
             check_bf16_out(A[k, i], np.maximum(z, 0.0), S, (shape, i, k))
@@ -150,7 +150,7 @@ def test_backward_layers_match_oracle(shape):
             z = cnn.conv3x3_input_grad(D[k, i], w) * (A[k - 1, i] > 0)
             S = cnn.conv3x3_input_grad(np.abs(D[k, i]), np.abs(w))
             check_bf16_out(D[k - 1, i], z, S, (shape, i, f"dz{k}"))
-        inputs = [bf16(b32[i])[None]] + [A[k, i] for k in range(5)]
+        inputs = [b32[i][None]] + [A[k, i] for k in range(5)]
         douts = [D[k, i] for k in range(5)] + [dout]
         for k in range(6):
             gw, gb = cnn.conv3x3_weight_grad(inputs[k], douts[k])
