@@ -265,6 +265,30 @@ hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, c
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
                             hipStream_t st);
 
+// ------------------------------------------------------ XCD-aware tile order
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
+// its own L2. Renumbering so that XCD k runs the contiguous range k*n/8 ..
+// (k+1)*n/8 of row-major tiles keeps a tile's halo neighbours in the same L2.
+// A bijection on [0, n) for every n.
+constexpr unsigned kXcds = 8;
+
+__device__ __forceinline__ unsigned xcd_remap(unsigned pid, unsigned n) {
+  const unsigned per = (n + kXcds - 1) / kXcds;
+  const unsigned tall = n % kXcds == 0 ? kXcds : n % kXcds;  // XCDs with `per` tiles
+  const unsigned xcd = pid % kXcds, local = pid / kXcds;
+  return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+}
+
+// (x, y, z) tile of this workgroup in a 3-D grid, XCD-aware.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty, int& tz) {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned n = gx * gy * gridDim.z;
+  const unsigned l = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), n);
+  tx = (int)(l % gx);
+  ty = (int)((l / gx) % gy);
+  tz = (int)(l / (gx * gy));
+}
+
 // ------------------------------------------------------------ warm-start CNN
 // Six 3x3 layers 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 (zero 'same' padding,
 // bias, ReLU on the first five). Master parameters are FP32, one flat vector

@@ -230,10 +230,12 @@ __global__ __launch_bounds__(512) void blur_tile_kernel(BlurArgs<T> a, const T* 
                                                         T* __restrict__ Y,
                                                         const T* __restrict__ SUB,
                                                         double* __restrict__ partials) {
-  double* po = partials ? partials + (long long)blockIdx.z * gridDim.x * gridDim.y +
-                              blockIdx.y * gridDim.x + blockIdx.x
-                        : nullptr;
-  blur_tile<T, R, ADJ, VAR>(a, X, Y, SUB, po, blockIdx.x, blockIdx.y, blockIdx.z);
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  double* po = partials
+                   ? partials + ((long long)tz * gridDim.y + ty) * gridDim.x + tx
+                   : nullptr;
+  blur_tile<T, R, ADJ, VAR>(a, X, Y, SUB, po, tx, ty, tz);
 }
 
 // One launch over tiles of several images: items[i] covers tiles
@@ -242,10 +244,11 @@ template <typename T, int R, bool ADJ, int VAR>
 __global__ __launch_bounds__(512) void blur_batch_kernel(const BlurItem<T>* __restrict__ items,
                                                          const int* __restrict__ prefix, int n,
                                                          const int* __restrict__ active) {
-  const int i = find_item(prefix, n, blockIdx.x);
+  const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int i = find_item(prefix, n, b);
   const BlurItem<T>& it = items[i];
   if (active && !active[it.image]) return;
-  const int t = blockIdx.x - prefix[i];
+  const int t = b - prefix[i];
   double* po = it.partials ? it.partials + t : nullptr;
   blur_tile<T, R, ADJ, VAR>(it.a, it.x, it.y, it.sub, po, t % it.tiles_x, t / it.tiles_x, 0);
 }
