@@ -3,6 +3,7 @@
 // (W^dagger)^*, R, R^*, A, A^*, one FISTA iteration and the convolution pair.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -135,6 +136,7 @@ struct WsLayout {
   size_t wave_end = 0;  // bytes used by the wavelet operators alone
   size_t total = 0;
   int n_pr = 0, n_pl = 0;
+  int n_pt = 0;  // FISTA l1 partials: one per analysis tile over all levels
 };
 
 WsLayout layout_ws(const WavePlan* p, const aw::BlurDesc* b, aw_dtype dt, int batch) {
@@ -168,10 +170,17 @@ WsLayout layout_ws(const WavePlan* p, const aw::BlurDesc* b, aw_dtype dt, int ba
   if (p) off = align_up(off + (size_t)p->ncoef * batch * ts);
   l.n_pr = b ? aw::blur_tiles(dt == AW_F64, *b) : 0;
   l.n_pl = p ? aw::fista_prox_blocks(p->ncoef) : 0;
+  if (p)
+    for (int j = 1; j <= p->J; ++j) {
+      aw::AnaLevel d{};
+      d.r = {p->sr[j - 1], p->sr[j], p->e};
+      d.c = {p->sc[j - 1], p->sc[j], p->e};
+      l.n_pt += aw::ana_level_tiles(dt == AW_F64, d);
+    }
   l.pr_off = off;
   off = align_up(off + (size_t)l.n_pr * batch * sizeof(double));
   l.pl_off = off;
-  off = align_up(off + (size_t)l.n_pl * batch * sizeof(double));
+  off = align_up(off + (size_t)std::max(l.n_pl, l.n_pt) * batch * sizeof(double));
   l.total = off;
   return l;
 }
@@ -256,6 +265,43 @@ aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* im
     d.bc = p.bc;
     d.pinv = pinv;
     hipError_t e = aw::launch_ana_level(dt == AW_F64, p.L, p.lo, d, batch, s);
+    if (e != hipSuccess) return hip_check(e, "analysis launch");
+  }
+  return AW_OK;
+}
+
+// W^* (pinv weights) of the residual image with the FISTA update fused into
+// every level's epilogue: x, y updated in place, l1 partials per tile.
+aw_status run_analysis_prox(const WavePlan& p, aw_dtype dt, int batch, const void* img, void* x,
+                            void* y, void* ws, const WsLayout& l, double inv_L, double thresh,
+                            double beta, double* partials, hipStream_t s) {
+  const size_t ts = dsize(dt);
+  int pbase = 0;
+  for (int j = 1; j <= p.J; ++j) {
+    aw::AnaLevel d{};
+    d.in = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
+    d.stride_in = (long long)p.sr[j - 1] * p.sc[j - 1];
+    d.a = (j == p.J) ? nullptr : wsp(ws, l.a_off[j]);
+    d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
+    d.hvd = nullptr;
+    d.stride_hvd = p.ncoef;
+    d.r = {p.sr[j - 1], p.sr[j], p.e};
+    d.c = {p.sc[j - 1], p.sc[j], p.e};
+    d.bc = p.bc;
+    d.pinv = 1;
+    aw::ProxEpi pe{};
+    pe.x_hvd = static_cast<char*>(x) + p.off_hvd[j] * ts;
+    pe.y_hvd = static_cast<char*>(y) + p.off_hvd[j] * ts;
+    pe.x_a = (j == p.J) ? x : nullptr;
+    pe.y_a = (j == p.J) ? y : nullptr;
+    pe.inv_L = inv_L;
+    pe.thresh = thresh;
+    pe.beta = beta;
+    pe.partials = partials;
+    pe.pbase = pbase;
+    pe.pstride = l.n_pt;
+    pbase += aw::ana_level_tiles(dt == AW_F64, d);
+    hipError_t e = aw::launch_ana_level_prox(dt == AW_F64, p.L, p.lo, d, pe, batch, s);
     if (e != hipSuccess) return hip_check(e, "analysis launch");
   }
   return AW_OK;
@@ -528,7 +574,6 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   hipStream_t s = (hipStream_t)stream;
   const int dtype_i = dtype == AW_F64;
   void* img = wsp(workspace, l.img_off);
-  void* grad = wsp(workspace, l.grad_off);
   double* pr = reinterpret_cast<double*>(wsp(workspace, l.pr_off));
   double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
   // r = R W y - b
@@ -541,20 +586,19 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   if ((st = hip_check(aw::launch_blur_adjoint(dtype_i, d, batch, state->resid, img, s),
                       "blur_adjoint launch")) != AW_OK)
     return st;
-  if ((st = run_analysis(p, dtype, batch, img, grad, workspace, l, 1, s)) != AW_OK) return st;
-  // prox + momentum
+  // W^* level by level, each level's gradient coefficients consumed at once
+  // by the prox + momentum update (the gradient never reaches memory)
   const double t = state->t;
   const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
   const double beta = (t - 1.0) / tn;
-  if ((st = hip_check(aw::launch_fista_prox(dtype_i, batch, p.ncoef, grad, state->x, state->y,
-                                            1.0 / L, lambda / L, beta, obj ? pl : nullptr, s),
-                      "prox launch")) != AW_OK)
+  if ((st = run_analysis_prox(p, dtype, batch, img, state->x, state->y, workspace, l, 1.0 / L,
+                              lambda / L, beta, obj ? pl : nullptr, s)) != AW_OK)
     return st;
   if (obj) {
     if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, state->obj, 2, 0, s),
                         "reduce launch")) != AW_OK)
       return st;
-    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pl, pl, 1.0, state->obj, 2, 1, s),
+    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pt, pl, 1.0, state->obj, 2, 1, s),
                         "reduce launch")) != AW_OK)
       return st;
   }

@@ -149,6 +149,21 @@ struct AnaLevel {
   int pinv;  // extension weights 1/mult (W^*) or 1 (W^dagger)
 };
 
+// FISTA update fused into an analysis level's epilogue: each gradient
+// coefficient g the level produces is consumed at once,
+//   x_k = soft(y_k - g inv_L, thresh),  y_{k+1} = x_k + beta (x_k - x_{k-1}),
+// in place in x and y (coefficient-vector layout, images stride_hvd apart),
+// with optional per-tile FP64 sums of |x_k|.
+struct ProxEpi {
+  void* x_hvd;  // x and y at this level's H band
+  void* y_hvd;
+  void* x_a;    // x and y at a_J (last level), else null: a_j is stored
+  void* y_a;
+  double inv_L, thresh, beta;
+  double* partials;  // [image][pstride]; this level's tiles at pbase + tile
+  int pbase, pstride;
+};
+
 // Fold of a materialised extended image (rows.N+2e x cols.N+2e) -> out.
 struct FoldLevel {
   const void* ext;
@@ -231,6 +246,10 @@ hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad
                              double inv_L, double thresh, double beta, double* partials,
                              hipStream_t s);
 int fista_prox_blocks(long long n);
+// Analysis level with the fused FISTA update (see ProxEpi); tiles per image.
+hipError_t launch_ana_level_prox(int dtype, int L, const double* lo, const AnaLevel& d,
+                                 const ProxEpi& pe, int batch, hipStream_t s);
+int ana_level_tiles(int dtype, const AnaLevel& d);
 // Per-block FP64 partials of ||x||_1 (same block count as the prox update).
 hipError_t launch_l1_partials(int dtype, int batch, long long n, const void* x, double* partials,
                               hipStream_t s);

@@ -417,10 +417,42 @@ hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLev
 }
 
 // ----------------------------------------------------------------- analysis
-template <typename T, int L, int BC, int VAR>
+template <typename T, int L, int BC, int VAR, bool PROX = false>
 __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, int bx, int by,
-                                         int img) {
+                                         int img, const ProxEpi& pe = ProxEpi{}) {
   constexpr int TKR = AnaTile<T, VAR>::TKR, TKC = AnaTile<T, VAR>::TKC, NT = AnaTile<T, VAR>::NT;
+  // output ownership of step 3: thread = column kk, KB consecutive rows
+  constexpr int RBLK = NT / TKC;
+  constexpr int KB = TKR / RBLK;
+  const int kk = threadIdx.x % TKC;
+  const int rb = threadIdx.x / TKC;
+  // fused update: y_k and x_{k-1} of the owned coefficients are fetched
+  // first, so their latency overlaps the staging below
+  T py[KB][4], px[KB][4];
+  if constexpr (PROX) {
+    const long long band = (long long)d.r.K * d.c.K;
+    const int kc = bx * TKC + kk;
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+      const int kr = by * TKR + rb * KB + r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) py[r][q] = px[r][q] = T(0);
+      if (kr < d.r.K && kc < d.c.K) {
+        const long long off = (long long)kr * d.c.K + kc;
+        const T* Y = static_cast<const T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
+        const T* X = static_cast<const T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          py[r][q] = Y[(q - 1) * band];
+          px[r][q] = X[(q - 1) * band];
+        }
+        if (pe.x_a) {
+          py[r][0] = static_cast<const T*>(pe.y_a)[(long long)img * d.stride_a + off];
+          px[r][0] = static_cast<const T*>(pe.x_a)[(long long)img * d.stride_a + off];
+        }
+      }
+    }
+  }
   constexpr int NWR = 2 * TKR + L - 2, NWC = 2 * TKC + L - 2;
   constexpr int VW = 16 / sizeof(T);                       // elements per 16-byte LDS read
   constexpr int SUS = ((NWC + VW - 1) / VW) * VW + VW;     // input row stride
@@ -568,11 +600,7 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
   __syncthreads();
 
   // 3. filter along rows: thread = column kc and KB consecutive coefficient rows
-  constexpr int RBLK = NT / TKC;
-  constexpr int KB = TKR / RBLK;
   constexpr int NW = 2 * KB + L - 2;
-  const int kk = threadIdx.x % TKC;
-  const int rb = threadIdx.x / TKC;
   V2 win[NW];
 #pragma unroll
   for (int i = 0; i < NW; ++i) win[i] = slh[(2 * rb * KB + i) * TKC + kk];
@@ -580,6 +608,7 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
   T* HVD = static_cast<T*>(d.hvd) + (long long)img * d.stride_hvd;
   const long long band = (long long)Kr * Kc;
   const int kc = kc0 + kk;
+  double l1 = 0.0;
 #pragma unroll
   for (int r = 0; r < KB; ++r) {
     T a = T(0), H = T(0), V = T(0), D = T(0);
@@ -594,10 +623,52 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
     const int kr = kr0 + rb * KB + r;
     if (kr < kr1 && kc < kc1) {
       const long long off = (long long)kr * Kc + kc;
-      Aout[off] = a;
-      HVD[off] = H;
-      HVD[band + off] = V;
-      HVD[2 * band + off] = D;
+      if constexpr (PROX) {
+        const T g[4] = {a, H, V, D};
+        T xn[4];
+        const T il = (T)pe.inv_L, th = (T)pe.thresh, be = (T)pe.beta;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T v = py[r][q] - g[q] * il;
+          xn[q] = v > th ? v - th : (v < -th ? v + th : T(0));
+        }
+        T* Xh = static_cast<T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
+        T* Yh = static_cast<T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          Yh[(q - 1) * band] = xn[q] + be * (xn[q] - px[r][q]);
+          Xh[(q - 1) * band] = xn[q];
+          l1 += (double)(xn[q] < T(0) ? -xn[q] : xn[q]);
+        }
+        if (pe.x_a) {
+          const long long oa = (long long)img * d.stride_a + off;
+          static_cast<T*>(pe.y_a)[oa] = xn[0] + be * (xn[0] - px[r][0]);
+          static_cast<T*>(pe.x_a)[oa] = xn[0];
+          l1 += (double)(xn[0] < T(0) ? -xn[0] : xn[0]);
+        } else {
+          Aout[off] = a;
+        }
+      } else {
+        Aout[off] = a;
+        HVD[off] = H;
+        HVD[band + off] = V;
+        HVD[2 * band + off] = D;
+      }
+    }
+  }
+  if constexpr (PROX) {
+    if (pe.partials) {  // fixed-order tile sum of |x_k|
+      __shared__ double red[NT];
+      red[threadIdx.x] = l1;
+      __syncthreads();
+      for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        const int gx = (Kc + TKC - 1) / TKC;
+        pe.partials[(long long)img * pe.pstride + pe.pbase + by * gx + bx] = red[0];
+      }
     }
   }
 }
@@ -607,6 +678,13 @@ __global__ __launch_bounds__(512) void ana_level_kernel(AnaLevel d, Taps<T> f) {
   int tx, ty, tz;
   xcd_tile(tx, ty, tz);
   ana_tile<T, L, BC, VAR>(d, f, tx, ty, tz);
+}
+
+template <typename T, int L, int BC>
+__global__ __launch_bounds__(512) void ana_prox_kernel(AnaLevel d, Taps<T> f, ProxEpi pe) {
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  ana_tile<T, L, BC, 0, true>(d, f, tx, ty, tz, pe);
 }
 
 template <typename T, int L, int BC, int VAR>
@@ -656,6 +734,53 @@ static hipError_t launch_ana_L(int L, const double* lo, const AnaLevel& d, int b
 hipError_t launch_ana_level(int dtype, int L, const double* lo, const AnaLevel& d, int batch,
                             hipStream_t s) {
   return dtype ? launch_ana_L<double>(L, lo, d, batch, s) : launch_ana_L<float>(L, lo, d, batch, s);
+}
+
+template <typename T, int L, int BC>
+static hipError_t launch_ana_prox_t(const double* lo, const AnaLevel& d, const ProxEpi& pe,
+                                    int batch, hipStream_t s) {
+  constexpr int TKR = AnaTile<T>::TKR, TKC = AnaTile<T>::TKC;
+  dim3 grid((d.c.K + TKC - 1) / TKC, (d.r.K + TKR - 1) / TKR, batch);
+  hipLaunchKernelGGL((ana_prox_kernel<T, L, BC>), grid, dim3(AnaTile<T>::NT), 0, s, d,
+                     make_taps<T>(lo, L), pe);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t launch_ana_prox_bc(const double* lo, const AnaLevel& d, const ProxEpi& pe,
+                                     int batch, hipStream_t s) {
+  switch (d.bc) {
+    case ZPD: return launch_ana_prox_t<T, L, ZPD>(lo, d, pe, batch, s);
+    case SYM: return launch_ana_prox_t<T, L, SYM>(lo, d, pe, batch, s);
+    case PER: return launch_ana_prox_t<T, L, PER>(lo, d, pe, batch, s);
+    case PER_EXT: return launch_ana_prox_t<T, L, PER_EXT>(lo, d, pe, batch, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_ana_prox_L(int L, const double* lo, const AnaLevel& d, const ProxEpi& pe,
+                                    int batch, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_ana_prox_bc<T, 2>(lo, d, pe, batch, s);
+    case 8: return launch_ana_prox_bc<T, 8>(lo, d, pe, batch, s);
+    case 16: return launch_ana_prox_bc<T, 16>(lo, d, pe, batch, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ana_level_prox(int dtype, int L, const double* lo, const AnaLevel& d,
+                                 const ProxEpi& pe, int batch, hipStream_t s) {
+  return dtype ? launch_ana_prox_L<double>(L, lo, d, pe, batch, s)
+               : launch_ana_prox_L<float>(L, lo, d, pe, batch, s);
+}
+
+int ana_level_tiles(int dtype, const AnaLevel& d) {
+  if (dtype)
+    return ((d.c.K + AnaTile<double>::TKC - 1) / AnaTile<double>::TKC) *
+           ((d.r.K + AnaTile<double>::TKR - 1) / AnaTile<double>::TKR);
+  return ((d.c.K + AnaTile<float>::TKC - 1) / AnaTile<float>::TKC) *
+         ((d.r.K + AnaTile<float>::TKR - 1) / AnaTile<float>::TKR);
 }
 
 // ------------------------------------------------------- batched launchers
