@@ -213,6 +213,22 @@ struct BlurArgs {
   T taps[2 * kMaxRadius + 1];  // correlation order: out[p] = sum_k t[k] in[p - r + k]
 };
 
+// Kernel taps of R (ADJ = false: the PSF reversed, so both directions run as
+// correlations) or R^* (the PSF as given); symmetric flags the vanishing
+// R^* border correction.
+template <typename T, bool ADJ>
+inline BlurArgs<T> make_blur_args(const BlurDesc& b) {
+  BlurArgs<T> a{};
+  a.rows = b.rows;
+  a.cols = b.cols;
+  const int K = 2 * b.radius + 1;
+  a.symmetric = 1;
+  for (int k = 0; k < K; ++k)
+    if (b.taps[k] != b.taps[K - 1 - k]) a.symmetric = 0;
+  for (int k = 0; k < K; ++k) a.taps[k] = (T)(ADJ ? b.taps[k] : b.taps[K - 1 - k]);
+  return a;
+}
+
 template <typename T>
 struct BlurItem {
   BlurArgs<T> a;

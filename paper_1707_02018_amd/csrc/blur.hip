@@ -264,19 +264,6 @@ int blur_tiles(int dtype, const BlurDesc& b) {
   return (int)(g.x * g.y);
 }
 
-template <typename T, bool ADJ>
-BlurArgs<T> make_blur_args(const BlurDesc& b) {
-  BlurArgs<T> a{};
-  a.rows = b.rows;
-  a.cols = b.cols;
-  const int K = 2 * b.radius + 1;
-  a.symmetric = 1;
-  for (int k = 0; k < K; ++k)
-    if (b.taps[k] != b.taps[K - 1 - k]) a.symmetric = 0;
-  // R: out[p] = sum_v g[v] x[p - v] -> correlation taps reversed; R^*: as given
-  for (int k = 0; k < K; ++k) a.taps[k] = (T)(ADJ ? b.taps[k] : b.taps[K - 1 - k]);
-  return a;
-}
 
 template <typename T, int R, bool ADJ>
 static hipError_t launch_r(const BlurDesc& b, int batch, const void* x, void* y, const void* sub,

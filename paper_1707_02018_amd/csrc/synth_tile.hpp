@@ -1,0 +1,333 @@
+// Synthesis tile machinery shared by the per-level kernels (wavelet.hip) and
+// the fused synthesis + blur kernel (fused.hip).
+#pragma once
+
+#include <cstdint>
+
+#include "aw_internal.hpp"
+
+namespace aw {
+
+// Tile shapes; variant 1 halves the rows (more, smaller tiles for small
+// levels). The batched path picks the variant per launch (autotuned).
+template <typename T, int V = 0>
+struct SynthTile {
+  static constexpr int TR = (sizeof(T) == 4 ? 32 : 16) >> V, TC = 64;
+};
+template <typename T, int V = 0>
+struct AnaTile {
+  static constexpr int TKR = (sizeof(T) == 4 ? 32 : 16) >> V, TKC = 32, NT = 512;
+};
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  using V2 = float2;
+  using V4 = float4;
+};
+template <>
+struct Vec<double> {
+  using V2 = double2;
+  using V4 = double4;
+};
+
+template <typename T>
+static Taps<T> make_taps(const double* lo, int L) {
+  Taps<T> t{};
+  for (int k = 0; k < L; ++k) {
+    t.h[k] = (T)lo[k];
+    t.g[k] = (T)(((k & 1) ? -1.0 : 1.0) * lo[L - 1 - k]);
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------- synthesis
+// Column-direction synthesis value of extended position n (any parity) from
+// the staged coefficient window; lo = a/H pair, hi = V/D pair.
+template <typename T, int L, int BC, typename V4>
+__device__ inline void synth_col_any(const V4* sc, int nkc, int j, int kw, int n, const Taps<T>& f,
+                                     T& lo, T& hi) {
+  const int base = synth_k0(n, L, BC) - kw;
+  const bool odd = n & 1;
+#pragma unroll
+  for (int m = 0; m < L / 2; ++m) {
+    const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
+    const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
+    const V4 q = sc[(base - m) * nkc + j];
+    lo += q.x * fh;
+    lo += q.y * fg;
+    hi += q.z * fh;
+    hi += q.w * fg;
+  }
+}
+
+template <typename T, int L, int BC, typename V2>
+__device__ inline T synth_row_any(const V2* row, int kw, int n, const Taps<T>& f) {
+  const int base = synth_k0(n, L, BC) - kw;
+  const bool odd = n & 1;
+  T acc = T(0);
+#pragma unroll
+  for (int m = 0; m < L / 2; ++m) {
+    const T fh = odd ? f.h[2 * m + 1] : f.h[2 * m];
+    const T fg = odd ? f.g[2 * m + 1] : f.g[2 * m];
+    const V2 q = row[base - m];
+    acc += q.x * fh;
+    acc += q.y * fg;
+  }
+  return acc;
+}
+
+// Split of a tile [p0, p1) (p0 even) into output pairs (p0 + 2s, p0 + 2s + 1):
+// pairs [sL, sR) are regular (single preimage p + e, both rows inside the
+// tile); the rows before 2 sL and from 2 sR on are handled one by one
+// (border rows within e of an edge, and a ragged last row). nsp counts them.
+__device__ inline void special_range(int p0, int p1, int N, int e, bool shift, int& sL, int& sR,
+                                     int& nsp) {
+  const int np = (p1 - p0 + 1) / 2;
+  sL = shift && e > p0 ? (e - p0 + 1) / 2 : 0;
+  if (sL > np) sL = np;
+  const int m = shift ? min(N - e, p1) : p1;
+  int r = (m - 1 - p0 + 1) / 2;  // ceil((m - 1 - p0) / 2) for m - 1 - p0 >= 0
+  if (m - 1 - p0 < 0) r = 0;
+  sR = r < sL ? sL : (r > np ? np : r);
+  nsp = 2 * sL + ((p1 - p0) - 2 * sR);
+}
+
+// t-th position (tile-relative) handled one by one
+__device__ inline int special_pos(int t, int sL, int sR) {
+  return t < 2 * sL ? t : 2 * sR + (t - 2 * sL);
+}
+
+// Synthesis of one level at the output rectangle [r0, r1) x [c0, c1)
+// (r0, c0 even) of image `img`; each output value goes to wr.one(row, col, v)
+// or, for a column pair (col even), wr.pair(row, col, v0, v1). smem_raw holds
+// the staged coefficient window (nkr x nkc x 4 values) followed by the
+// column-pass rows ((r1 - r0) x nkc x 2 values).
+template <typename T, int L, int BC, typename W>
+__device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f, int r0, int r1,
+                                           int c0, int c1, int img, unsigned char* smem_raw,
+                                           W& wr) {
+  constexpr int HL = L / 2;
+  // extended modes shift the signal by e = L - 1 (odd): the first row of a
+  // pair has odd n and the second row uses the next coefficient row
+  constexpr bool SHIFT = (BC == SYM);
+  using V2 = typename Vec<T>::V2;
+  using V4 = typename Vec<T>::V4;
+
+  const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
+  const int er = SHIFT ? d.r.e : 0;
+  const int ec = SHIFT ? d.c.e : 0;
+  int nlo_r, nhi_r, nlo_c, nhi_c;
+  fold_window(r0, r1, Nr, er, nlo_r, nhi_r);
+  fold_window(c0, c1, Nc, ec, nlo_c, nhi_c);
+  const int kwr = synth_k0(nlo_r, L, BC) - (HL - 1);
+  const int nkr = synth_k0(nhi_r - 1, L, BC) + 1 - kwr;
+  const int kwc = synth_k0(nlo_c, L, BC) - (HL - 1);
+  const int nkc = synth_k0(nhi_c - 1, L, BC) + 1 - kwc;
+
+  V4* sc = reinterpret_cast<V4*>(smem_raw);  // [nkr][nkc] (a, H, V, D)
+  V2* st = reinterpret_cast<V2*>(sc + nkr * nkc);  // [TR][nkc] (lo, hi) after the row fold
+
+  const T* A = static_cast<const T*>(d.a) + (long long)img * d.stride_a;
+  const T* HVD = static_cast<const T*>(d.hvd) + (long long)img * d.stride_hvd;
+  const long long band = (long long)Kr * Kc;
+
+  // 1. stage the coefficient window, bands interleaved; each thread issues a
+  //    batch of loads before writing LDS
+  constexpr int CH = 4;
+  for (int base = 0; base < nkr * nkc; base += 512 * CH) {
+    V4 q[CH];
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int idx = base + threadIdx.x + it * 512;
+      q[it].x = q[it].y = q[it].z = q[it].w = T(0);
+      if (idx < nkr * nkc) {
+        const int i = idx / nkc;
+        const int j = idx - i * nkc;
+        int kr = kwr + i, kc = kwc + j;
+        bool ok;
+        if (BC == PER) {
+          kr = posmod(kr, Kr);
+          kc = posmod(kc, Kc);
+          ok = true;
+        } else {
+          ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
+        }
+        if (ok) {
+          const long long off = (long long)kr * Kc + kc;
+          q[it].x = A[off];
+          q[it].y = HVD[off];
+          q[it].z = HVD[band + off];
+          q[it].w = HVD[2 * band + off];
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int idx = base + threadIdx.x + it * 512;
+      if (idx < nkr * nkc) sc[idx] = q[it];
+    }
+  }
+  __syncthreads();
+
+  // 2. column-direction synthesis. Regular row pairs (single preimage, both
+  //    rows in the tile) run the paired fast path; border rows and a ragged
+  //    last row run a separate pass, so no wave mixes the two.
+  int sL, sR, nsp;
+  special_range(r0, r1, Nr, er, SHIFT, sL, sR, nsp);
+  for (int item = threadIdx.x; item < (sR - sL) * nkc; item += blockDim.x) {
+    const int s = sL + item / nkc;
+    const int j = item - (item / nkc) * nkc;
+    const int p0 = r0 + 2 * s;
+    T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
+    const int k1 = synth_k0(p0 + er, L, BC) - kwr;
+    if (SHIFT) {  // row p0: odd taps at k1; row p0+1: even taps at k1+1
+      V4 q[HL + 1];
+#pragma unroll
+      for (int m = 0; m <= HL; ++m) q[m] = sc[(k1 + 1 - m) * nkc + j];
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        lo0 += q[m + 1].x * f.h[2 * m + 1];
+        lo0 += q[m + 1].y * f.g[2 * m + 1];
+        hi0 += q[m + 1].z * f.h[2 * m + 1];
+        hi0 += q[m + 1].w * f.g[2 * m + 1];
+        lo1 += q[m].x * f.h[2 * m];
+        lo1 += q[m].y * f.g[2 * m];
+        hi1 += q[m].z * f.h[2 * m];
+        hi1 += q[m].w * f.g[2 * m];
+      }
+    } else {  // both rows share k1: even taps, then odd taps
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        const V4 q = sc[(k1 - m) * nkc + j];
+        lo0 += q.x * f.h[2 * m];
+        lo0 += q.y * f.g[2 * m];
+        hi0 += q.z * f.h[2 * m];
+        hi0 += q.w * f.g[2 * m];
+        lo1 += q.x * f.h[2 * m + 1];
+        lo1 += q.y * f.g[2 * m + 1];
+        hi1 += q.z * f.h[2 * m + 1];
+        hi1 += q.w * f.g[2 * m + 1];
+      }
+    }
+    V2 v0, v1;
+    v0.x = lo0;
+    v0.y = hi0;
+    v1.x = lo1;
+    v1.y = hi1;
+    st[(2 * s) * nkc + j] = v0;
+    st[(2 * s + 1) * nkc + j] = v1;
+  }
+  // border rows: p + e and, near an edge, the reflected preimage
+  // (e - 1 - p on the left, 2N - 1 - p + e on the right), weighted 1/mult
+  for (int item = threadIdx.x; item < nsp * nkc; item += blockDim.x) {
+    const int t = item / nkc;
+    const int j = item - t * nkc;
+    const int pr = special_pos(t, sL, sR);
+    const int p = r0 + pr;
+    T lo = T(0), hi = T(0);
+    int cnt = 1;
+    synth_col_any<T, L, BC>(sc, nkc, j, kwr, p + er, f, lo, hi);
+    if (SHIFT && p < er) {
+      synth_col_any<T, L, BC>(sc, nkc, j, kwr, er - 1 - p, f, lo, hi);
+      ++cnt;
+    }
+    if (SHIFT && p >= Nr - er) {
+      synth_col_any<T, L, BC>(sc, nkc, j, kwr, 2 * Nr - 1 - p + er, f, lo, hi);
+      ++cnt;
+    }
+    if (d.pinv && cnt > 1) {
+      const T wgt = cnt == 2 ? T(0.5) : T(1) / T(cnt);
+      lo *= wgt;
+      hi *= wgt;
+    }
+    V2 v;
+    v.x = lo;
+    v.y = hi;
+    st[pr * nkc + j] = v;
+  }
+  __syncthreads();
+
+  // 3. row-direction synthesis, same split over columns
+  int qL, qR, nsc;
+  special_range(c0, c1, Nc, ec, SHIFT, qL, qR, nsc);
+  const int QC = (c1 - c0 + 1) / 2;
+  const int nrows = r1 - r0;
+  for (int item = threadIdx.x; item < nrows * QC; item += blockDim.x) {
+    const int pr = item / QC;
+    const int q = item - pr * QC;
+    if (q < qL || q >= qR) continue;
+    const int p = c0 + 2 * q;
+    const V2* row = st + pr * nkc;
+    T o0 = T(0), o1 = T(0);
+    const int k1 = synth_k0(p + ec, L, BC) - kwc;
+    if (SHIFT) {
+      V2 w[HL + 1];
+#pragma unroll
+      for (int m = 0; m <= HL; ++m) w[m] = row[k1 + 1 - m];
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        o0 += w[m + 1].x * f.h[2 * m + 1];
+        o0 += w[m + 1].y * f.g[2 * m + 1];
+        o1 += w[m].x * f.h[2 * m];
+        o1 += w[m].y * f.g[2 * m];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        const V2 w = row[k1 - m];
+        o0 += w.x * f.h[2 * m];
+        o0 += w.y * f.g[2 * m];
+        o1 += w.x * f.h[2 * m + 1];
+        o1 += w.y * f.g[2 * m + 1];
+      }
+    }
+    wr.pair(r0 + pr, p, o0, o1);
+  }
+  for (int item = threadIdx.x; item < nrows * nsc; item += blockDim.x) {
+    const int pr = item / nsc;
+    const int t = item - pr * nsc;
+    const int p = c0 + special_pos(t, qL, qR);
+    const V2* row = st + pr * nkc;
+    T acc = synth_row_any<T, L, BC>(row, kwc, p + ec, f);
+    int cnt = 1;
+    if (SHIFT && p < ec) {
+      acc += synth_row_any<T, L, BC>(row, kwc, ec - 1 - p, f);
+      ++cnt;
+    }
+    if (SHIFT && p >= Nc - ec) {
+      acc += synth_row_any<T, L, BC>(row, kwc, 2 * Nc - 1 - p + ec, f);
+      ++cnt;
+    }
+    if (d.pinv && cnt > 1) acc *= cnt == 2 ? T(0.5) : T(1) / T(cnt);
+    wr.one(r0 + pr, p, acc);
+  }
+}
+
+// Output of synth_rect into a row-major plane (rows of Nc values).
+template <typename T>
+struct PlaneWriter {
+  using V2 = typename Vec<T>::V2;
+  T* O;
+  int Nc;
+  bool pair_store;  // 2-element stores keep their alignment on every row
+  __device__ PlaneWriter(T* o, int nc)
+      : O(o), Nc(nc),
+        pair_store((nc & 1) == 0 && (reinterpret_cast<uintptr_t>(o) & (sizeof(V2) - 1)) == 0) {}
+  __device__ void pair(int r, int c, T v0, T v1) {
+    T* row = O + (long long)r * Nc;
+    if (pair_store) {
+      V2 o;
+      o.x = v0;
+      o.y = v1;
+      *reinterpret_cast<V2*>(row + c) = o;
+    } else {
+      row[c] = v0;
+      row[c + 1] = v1;
+    }
+  }
+  __device__ void one(int r, int c, T v) { O[(long long)r * Nc + c] = v; }
+};
+
+}  // namespace aw
