@@ -175,7 +175,7 @@ WsLayout layout_ws(const WavePlan* p, const aw::BlurDesc* b, aw_dtype dt, int ba
       aw::AnaLevel d{};
       d.r = {p->sr[j - 1], p->sr[j], p->e};
       d.c = {p->sc[j - 1], p->sc[j], p->e};
-      l.n_pt += aw::ana_level_tiles(dt == AW_F64, d);
+      l.n_pt += aw::ana_level_tiles(dt == AW_F64, d, batch);
     }
   l.pr_off = off;
   off = align_up(off + (size_t)l.n_pr * batch * sizeof(double));
@@ -300,7 +300,7 @@ aw_status run_analysis_prox(const WavePlan& p, aw_dtype dt, int batch, const voi
     pe.partials = partials;
     pe.pbase = pbase;
     pe.pstride = l.n_pt;
-    pbase += aw::ana_level_tiles(dt == AW_F64, d);
+    pbase += aw::ana_level_tiles(dt == AW_F64, d, batch);
     hipError_t e = aw::launch_ana_level_prox(dt == AW_F64, p.L, p.lo, d, pe, batch, s);
     if (e != hipSuccess) return hip_check(e, "analysis launch");
   }

@@ -265,7 +265,7 @@ int fista_prox_blocks(long long n);
 // Analysis level with the fused FISTA update (see ProxEpi); tiles per image.
 hipError_t launch_ana_level_prox(int dtype, int L, const double* lo, const AnaLevel& d,
                                  const ProxEpi& pe, int batch, hipStream_t s);
-int ana_level_tiles(int dtype, const AnaLevel& d);
+int ana_level_tiles(int dtype, const AnaLevel& d, int batch);
 // Per-block FP64 partials of ||x||_1 (same block count as the prox update).
 hipError_t launch_l1_partials(int dtype, int batch, long long n, const void* x, double* partials,
                               hipStream_t s);
