@@ -194,22 +194,45 @@ aw_status need_ws(void* ws, size_t have, size_t need) {
 }
 
 // ---------------------------------------------------------- level sequences
-aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* coef, void* img,
-                        void* ws, const WsLayout& l, int pinv, hipStream_t s) {
+aw::SynthLevel synth_desc(const WavePlan& p, aw_dtype dt, const void* coef, void* img, void* ws,
+                          const WsLayout& l, int pinv, int j) {
   const size_t ts = dsize(dt);
+  aw::SynthLevel d{};
+  d.a = (j == p.J) ? coef : wsp(ws, l.a_off[j]);
+  d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
+  d.hvd = static_cast<const char*>(coef) + p.off_hvd[j] * ts;
+  d.stride_hvd = p.ncoef;
+  d.out = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
+  d.stride_out = (long long)p.sr[j - 1] * p.sc[j - 1];
+  d.r = {p.sr[j - 1], p.sr[j], p.e};
+  d.c = {p.sc[j - 1], p.sc[j], p.e};
+  d.bc = p.bc;
+  d.pinv = pinv;
+  return d;
+}
+
+aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* coef, void* img,
+                        void* ws, const WsLayout& l, int pinv, hipStream_t s, int j_lo = 1) {
   const int dtype = dt == AW_F64;
-  for (int j = p.J; j >= 1; --j) {
-    aw::SynthLevel d{};
-    d.a = (j == p.J) ? coef : wsp(ws, l.a_off[j]);
-    d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
-    d.hvd = static_cast<const char*>(coef) + p.off_hvd[j] * ts;
-    d.stride_hvd = p.ncoef;
-    d.out = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
-    d.stride_out = (long long)p.sr[j - 1] * p.sc[j - 1];
-    d.r = {p.sr[j - 1], p.sr[j], p.e};
-    d.c = {p.sc[j - 1], p.sc[j], p.e};
-    d.bc = p.bc;
-    d.pinv = pinv;
+  // levels min(J, 4) .. 2 in one chained launch where supported
+  int chain_top = 0;
+  size_t chain_lds = 0;
+  aw::SynthChain ch{};
+  if (j_lo <= 2 && p.J >= 3) {
+    chain_top = std::min(p.J, 1 + aw::kChainMax);
+    ch.nl = chain_top - 1;
+    for (int k = 0; k < ch.nl; ++k) ch.d[k] = synth_desc(p, dt, coef, img, ws, l, pinv, 2 + k);
+    chain_lds = aw::synth_chain_plan(dtype, p.L, ch);
+    if (!chain_lds) chain_top = 0;
+  }
+  for (int j = p.J; j >= j_lo; --j) {
+    if (chain_top && j == chain_top) {
+      hipError_t e = aw::launch_synth_chain(p.L, p.lo, ch, chain_lds, batch, s);
+      if (e != hipSuccess) return hip_check(e, "synthesis launch");
+      j = 2;  // levels chain_top .. 2 done
+      continue;
+    }
+    aw::SynthLevel d = synth_desc(p, dt, coef, img, ws, l, pinv, j);
     hipError_t e;
     // the tile kernel folds with closed-form preimages, valid when every
     // extended sample is at most one reflection away (N >= e); periodic

@@ -138,6 +138,17 @@ struct SynthLevel {
   int pinv;  // fold weights 1/mult (1) or 1 (0)
 };
 
+// Consecutive synthesis levels run as one launch: d[0] is the finest (its
+// output goes to memory), d[k] the k-th coarser one (its output, the
+// approximation band of d[k-1], stays in LDS).
+constexpr int kChainMax = 3;
+struct SynthChain {
+  SynthLevel d[kChainMax];
+  int nl;
+  unsigned buf_off[kChainMax];  // LDS byte offsets of the band buffers
+  int buf_pitch[kChainMax];     // their row pitches (elements)
+};
+
 // One analysis level: in (rows.N x cols.N) -> (a, H, V, D).
 struct AnaLevel {
   const void* in;
@@ -262,6 +273,11 @@ hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad
                              double inv_L, double thresh, double beta, double* partials,
                              hipStream_t s);
 int fista_prox_blocks(long long n);
+// Chained synthesis (FP32, zpd / sym without the two-step fold): fills the
+// chain's LDS plan and returns its dynamic LDS bytes (0: not supported).
+size_t synth_chain_plan(int dtype, int L, SynthChain& c);
+hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size_t lds, int batch,
+                              hipStream_t s);
 // Analysis level with the fused FISTA update (see ProxEpi); tiles per image.
 hipError_t launch_ana_level_prox(int dtype, int L, const double* lo, const AnaLevel& d,
                                  const ProxEpi& pe, int batch, hipStream_t s);

@@ -99,15 +99,40 @@ __device__ inline int special_pos(int t, int sL, int sR) {
   return t < 2 * sL ? t : 2 * sR + (t - 2 * sL);
 }
 
+// Coefficient window [kw, kw + nk) of one axis that the synthesis outputs
+// [p0, p1) read (e_eff = e for the symmetric extension, else 0), and the part
+// of it inside the band, widened to an even start: [a0, a1).
+__host__ __device__ inline void synth_axis_window(int p0, int p1, int N, int e_eff, int L, int bc,
+                                                  int& kw, int& nk) {
+  int nlo, nhi;
+  fold_window(p0, p1, N, e_eff, nlo, nhi);
+  kw = synth_k0(nlo, L, bc) - (L / 2 - 1);
+  nk = synth_k0(nhi - 1, L, bc) + 1 - kw;
+}
+
+__host__ __device__ inline void synth_band_part(int kw, int nk, int K, int& a0, int& a1) {
+  a0 = (kw > 0 ? kw : 0) & ~1;
+  a1 = kw + nk < K ? kw + nk : K;
+}
+
+// A level's approximation band held in LDS over rows [r0, ..) and columns
+// [c0, ..) (row pitch `pitch`), in place of the band in memory.
+template <typename T>
+struct LdsBand {
+  const T* p;
+  int r0, c0, pitch;
+};
+
 // Synthesis of one level at the output rectangle [r0, r1) x [c0, c1)
 // (r0, c0 even) of image `img`; each output value goes to wr.one(row, col, v)
 // or, for a column pair (col even), wr.pair(row, col, v0, v1). smem_raw holds
 // the staged coefficient window (nkr x nkc x 4 values) followed by the
-// column-pass rows ((r1 - r0) x nkc x 2 values).
+// column-pass rows ((r1 - r0) x nkc x 2 values). With abuf, the approximation
+// band comes from LDS (it must cover the window's part inside the band).
 template <typename T, int L, int BC, typename W>
 __device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f, int r0, int r1,
                                            int c0, int c1, int img, unsigned char* smem_raw,
-                                           W& wr) {
+                                           W& wr, const LdsBand<T>* abuf = nullptr) {
   constexpr int HL = L / 2;
   // extended modes shift the signal by e = L - 1 (odd): the first row of a
   // pair has odd n and the second row uses the next coefficient row
@@ -118,13 +143,9 @@ __device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f
   const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
   const int er = SHIFT ? d.r.e : 0;
   const int ec = SHIFT ? d.c.e : 0;
-  int nlo_r, nhi_r, nlo_c, nhi_c;
-  fold_window(r0, r1, Nr, er, nlo_r, nhi_r);
-  fold_window(c0, c1, Nc, ec, nlo_c, nhi_c);
-  const int kwr = synth_k0(nlo_r, L, BC) - (HL - 1);
-  const int nkr = synth_k0(nhi_r - 1, L, BC) + 1 - kwr;
-  const int kwc = synth_k0(nlo_c, L, BC) - (HL - 1);
-  const int nkc = synth_k0(nhi_c - 1, L, BC) + 1 - kwc;
+  int kwr, nkr, kwc, nkc;
+  synth_axis_window(r0, r1, Nr, er, L, BC, kwr, nkr);
+  synth_axis_window(c0, c1, Nc, ec, L, BC, kwc, nkc);
 
   V4* sc = reinterpret_cast<V4*>(smem_raw);  // [nkr][nkc] (a, H, V, D)
   V2* st = reinterpret_cast<V2*>(sc + nkr * nkc);  // [TR][nkc] (lo, hi) after the row fold
@@ -156,7 +177,7 @@ __device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f
         }
         if (ok) {
           const long long off = (long long)kr * Kc + kc;
-          q[it].x = A[off];
+          q[it].x = abuf ? abuf->p[(kr - abuf->r0) * abuf->pitch + (kc - abuf->c0)] : A[off];
           q[it].y = HVD[off];
           q[it].z = HVD[band + off];
           q[it].w = HVD[2 * band + off];
@@ -328,6 +349,19 @@ struct PlaneWriter {
     }
   }
   __device__ void one(int r, int c, T v) { O[(long long)r * Nc + c] = v; }
+};
+
+// Output of synth_rect into an LDS region (rows from r0, columns from c0).
+template <typename T>
+struct LdsWriter {
+  T* p;
+  int r0, c0, pitch;
+  __device__ void one(int r, int c, T v) { p[(r - r0) * pitch + (c - c0)] = v; }
+  __device__ void pair(int r, int c, T v0, T v1) {
+    T* q = p + (r - r0) * pitch + (c - c0);
+    q[0] = v0;
+    q[1] = v1;
+  }
 };
 
 }  // namespace aw

@@ -13,6 +13,7 @@
 // the extended input window (extension index map and 1/mult weights applied
 // during the gather), filters along columns into LDS, then along rows, and
 // writes a, H, V, D.
+#include <algorithm>
 #include <type_traits>
 
 #include "aw_internal.hpp"
@@ -118,6 +119,133 @@ hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLev
                               hipStream_t s) {
   return dtype ? launch_synth_L<double>(L, lo, d, batch, s)
                : launch_synth_L<float>(L, lo, d, batch, s);
+}
+
+// ------------------------------------------------ chained small levels
+// The coarse synthesis levels are small and latency-bound: one launch per
+// level costs a launch and a memory round trip each. The chain kernel runs
+// d[nl-1] .. d[0] in one launch: a workgroup owns a tile of d[0]'s output and
+// synthesises, coarse to fine, the parts of the intermediate approximation
+// bands that tile needs (halos recomputed) into LDS. Every value is computed
+// by the same arithmetic as the per-level kernels, so the result is bitwise
+// the same.
+template <typename T, int L, int BC>
+__global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int TR = SynthTile<T>::TR, TC = SynthTile<T>::TC;
+  const int img = blockIdx.z;
+  // rows [ra[k], rb[k]) x columns [ca[k], cb[k]) of level d[k]'s output
+  int ra[kChainMax], rb[kChainMax], ca[kChainMax], cb[kChainMax];
+  ra[0] = blockIdx.y * TR;
+  rb[0] = min(ra[0] + TR, c.d[0].r.N);
+  ca[0] = blockIdx.x * TC;
+  cb[0] = min(ca[0] + TC, c.d[0].c.N);
+#pragma unroll
+  for (int k = 0; k + 1 < kChainMax; ++k) {
+    if (k + 1 >= c.nl) break;
+    int kw, nk;
+    synth_axis_window(ra[k], rb[k], c.d[k].r.N, BC == SYM ? c.d[k].r.e : 0, L, BC, kw, nk);
+    synth_band_part(kw, nk, c.d[k].r.K, ra[k + 1], rb[k + 1]);
+    synth_axis_window(ca[k], cb[k], c.d[k].c.N, BC == SYM ? c.d[k].c.e : 0, L, BC, kw, nk);
+    synth_band_part(kw, nk, c.d[k].c.K, ca[k + 1], cb[k + 1]);
+  }
+  for (int k = c.nl - 1; k >= 1; --k) {
+    LdsWriter<T> wr{reinterpret_cast<T*>(smem_raw + c.buf_off[k - 1]), ra[k], ca[k],
+                    c.buf_pitch[k - 1]};
+    if (k == c.nl - 1) {
+      synth_rect<T, L, BC>(c.d[k], f, ra[k], rb[k], ca[k], cb[k], img, smem_raw, wr);
+    } else {
+      const LdsBand<T> src{reinterpret_cast<const T*>(smem_raw + c.buf_off[k]), ra[k + 1],
+                           ca[k + 1], c.buf_pitch[k]};
+      synth_rect<T, L, BC>(c.d[k], f, ra[k], rb[k], ca[k], cb[k], img, smem_raw, wr, &src);
+    }
+    __syncthreads();
+  }
+  PlaneWriter<T> out(static_cast<T*>(c.d[0].out) + (long long)img * c.d[0].stride_out,
+                     c.d[0].c.N);
+  const LdsBand<T> src{reinterpret_cast<const T*>(smem_raw + c.buf_off[0]), ra[1], ca[1],
+                       c.buf_pitch[0]};
+  synth_rect<T, L, BC>(c.d[0], f, ra[0], rb[0], ca[0], cb[0], img, smem_raw, out, &src);
+}
+
+// Largest output part, and coefficient window, of each chained level over
+// the tiles of one axis (rows: is_row).
+template <int L, int BC>
+static void chain_axis(const SynthChain& c, bool is_row, int tile, int len[], int nk[]) {
+  for (int k = 0; k < c.nl; ++k) len[k] = nk[k] = 0;
+  const Axis& a0 = is_row ? c.d[0].r : c.d[0].c;
+  for (int p0 = 0; p0 < a0.N; p0 += tile) {
+    int lo = p0, hi = std::min(p0 + tile, a0.N);
+    for (int k = 0; k < c.nl; ++k) {
+      const Axis& a = is_row ? c.d[k].r : c.d[k].c;
+      len[k] = std::max(len[k], hi - lo);
+      int kw, n;
+      synth_axis_window(lo, hi, a.N, BC == SYM ? a.e : 0, L, BC, kw, n);
+      nk[k] = std::max(nk[k], n);
+      synth_band_part(kw, n, a.K, lo, hi);
+    }
+  }
+}
+
+template <int L, int BC>
+static size_t chain_plan_t(SynthChain& c) {
+  using T = float;
+  int lr[kChainMax], nr[kChainMax], lc[kChainMax], nc[kChainMax];
+  chain_axis<L, BC>(c, true, SynthTile<T>::TR, lr, nr);
+  chain_axis<L, BC>(c, false, SynthTile<T>::TC, lc, nc);
+  size_t scratch = 0;
+  for (int k = 0; k < c.nl; ++k)
+    scratch = std::max(scratch, sizeof(T) * (size_t)(4 * nr[k] * nc[k] + 2 * lr[k] * nc[k]));
+  size_t off = (scratch + 15) / 16 * 16;
+  for (int k = 0; k + 1 < c.nl; ++k) {  // buffer k: output of d[k+1]
+    c.buf_off[k] = (unsigned)off;
+    c.buf_pitch[k] = lc[k + 1];
+    off += ((size_t)lr[k + 1] * lc[k + 1] * sizeof(T) + 15) / 16 * 16;
+  }
+  return off;
+}
+
+size_t synth_chain_plan(int dtype, int L, SynthChain& c) {
+  if (dtype != 0 || c.nl < 2 || c.nl > kChainMax) return 0;
+  const int bc = c.d[0].bc;
+  for (int k = 0; k < c.nl; ++k) {
+    if (c.d[k].bc != bc) return 0;
+    if (bc == SYM && (c.d[k].r.N < c.d[k].r.e || c.d[k].c.N < c.d[k].c.e)) return 0;
+  }
+  size_t lds = 0;
+  if (bc == SYM) {
+    lds = L == 2 ? chain_plan_t<2, SYM>(c) : L == 8 ? chain_plan_t<8, SYM>(c)
+                                                    : L == 16 ? chain_plan_t<16, SYM>(c) : 0;
+  } else if (bc == ZPD) {
+    lds = L == 2 ? chain_plan_t<2, ZPD>(c) : L == 8 ? chain_plan_t<8, ZPD>(c)
+                                                    : L == 16 ? chain_plan_t<16, ZPD>(c) : 0;
+  }
+  return lds <= 64 * 1024 ? lds : 0;
+}
+
+template <int L, int BC>
+static hipError_t launch_chain_t(const double* lo, const SynthChain& c, size_t lds, int batch,
+                                 hipStream_t s) {
+  using T = float;
+  dim3 grid((c.d[0].c.N + SynthTile<T>::TC - 1) / SynthTile<T>::TC,
+            (c.d[0].r.N + SynthTile<T>::TR - 1) / SynthTile<T>::TR, batch);
+  hipLaunchKernelGGL((synth_chain_kernel<T, L, BC>), grid, dim3(512), lds, s, c,
+                     make_taps<T>(lo, L));
+  return hipGetLastError();
+}
+
+hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size_t lds, int batch,
+                              hipStream_t s) {
+  const int bc = c.d[0].bc;
+  switch (L) {
+    case 2: return bc == SYM ? launch_chain_t<2, SYM>(lo, c, lds, batch, s)
+                             : launch_chain_t<2, ZPD>(lo, c, lds, batch, s);
+    case 8: return bc == SYM ? launch_chain_t<8, SYM>(lo, c, lds, batch, s)
+                             : launch_chain_t<8, ZPD>(lo, c, lds, batch, s);
+    case 16: return bc == SYM ? launch_chain_t<16, SYM>(lo, c, lds, batch, s)
+                              : launch_chain_t<16, ZPD>(lo, c, lds, batch, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ----------------------------------------------------------------- analysis
