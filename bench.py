@@ -45,10 +45,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fista2048_sym.md")
 
 
 def source_hash(name: str) -> str:
+    """Hash of a kernel source file and every internal header it can include."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1707_02018_amd", "csrc")
     h = hashlib.sha256()
-    for f in (name, "aw_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1707_02018_amd", "csrc", f), "rb") as fh:
+    for f in [name] + sorted(x for x in os.listdir(csrc) if x.endswith(".hpp")):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

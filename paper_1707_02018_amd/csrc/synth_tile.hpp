@@ -123,6 +123,76 @@ struct LdsBand {
   int r0, c0, pitch;
 };
 
+// Geometry of one synthesis rectangle: outputs [r0, r1) x [c0, c1) of image
+// img, read from the coefficient window [kwr, kwr + nkr) x [kwc, kwc + nkc).
+struct SynthWin {
+  int r0, r1, c0, c1, img, kwr, nkr, kwc, nkc;
+};
+
+template <int L, int BC>
+__device__ __forceinline__ SynthWin synth_win(const SynthLevel& d, int r0, int r1, int c0, int c1,
+                                              int img) {
+  SynthWin w{r0, r1, c0, c1, img, 0, 0, 0, 0};
+  synth_axis_window(r0, r1, d.r.N, BC == SYM ? d.r.e : 0, L, BC, w.kwr, w.nkr);
+  synth_axis_window(c0, c1, d.c.N, BC == SYM ? d.c.e : 0, L, BC, w.kwc, w.nkc);
+  return w;
+}
+
+constexpr int kSynthCH = 4;  // window items per thread per load batch (x 512 threads)
+
+// Loads of window items base + threadIdx.x + it * 512 (bands interleaved:
+// a, H, V, D), zero outside the bands.
+template <typename T, int L, int BC>
+__device__ __forceinline__ void synth_load(const SynthLevel& d, const SynthWin& w, int base,
+                                           typename Vec<T>::V4 (&q)[kSynthCH],
+                                           const LdsBand<T>* abuf) {
+  const int Kr = d.r.K, Kc = d.c.K;
+  const T* A = static_cast<const T*>(d.a) + (long long)w.img * d.stride_a;
+  const T* HVD = static_cast<const T*>(d.hvd) + (long long)w.img * d.stride_hvd;
+  const long long band = (long long)Kr * Kc;
+#pragma unroll
+  for (int it = 0; it < kSynthCH; ++it) {
+    const int idx = base + threadIdx.x + it * 512;
+    q[it].x = q[it].y = q[it].z = q[it].w = T(0);
+    if (idx < w.nkr * w.nkc) {
+      const int i = idx / w.nkc;
+      const int j = idx - i * w.nkc;
+      int kr = w.kwr + i, kc = w.kwc + j;
+      bool ok;
+      if (BC == PER) {
+        kr = posmod(kr, Kr);
+        kc = posmod(kc, Kc);
+        ok = true;
+      } else {
+        ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
+      }
+      if (ok) {
+        const long long off = (long long)kr * Kc + kc;
+        q[it].x = abuf ? abuf->p[(kr - abuf->r0) * abuf->pitch + (kc - abuf->c0)] : A[off];
+        q[it].y = HVD[off];
+        q[it].z = HVD[band + off];
+        q[it].w = HVD[2 * band + off];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void synth_put(const SynthWin& w, int base,
+                                          const typename Vec<T>::V4 (&q)[kSynthCH],
+                                          unsigned char* smem_raw) {
+  auto* sc = reinterpret_cast<typename Vec<T>::V4*>(smem_raw);
+#pragma unroll
+  for (int it = 0; it < kSynthCH; ++it) {
+    const int idx = base + threadIdx.x + it * 512;
+    if (idx < w.nkr * w.nkc) sc[idx] = q[it];
+  }
+}
+
+template <typename T, int L, int BC, typename W>
+__device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>& f,
+                                             const SynthWin& w, unsigned char* smem_raw, W& wr);
+
 // Synthesis of one level at the output rectangle [r0, r1) x [c0, c1)
 // (r0, c0 even) of image `img`; each output value goes to wr.one(row, col, v)
 // or, for a column pair (col even), wr.pair(row, col, v0, v1). smem_raw holds
@@ -133,64 +203,35 @@ template <typename T, int L, int BC, typename W>
 __device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f, int r0, int r1,
                                            int c0, int c1, int img, unsigned char* smem_raw,
                                            W& wr, const LdsBand<T>* abuf = nullptr) {
+  const SynthWin w = synth_win<L, BC>(d, r0, r1, c0, c1, img);
+  // 1. stage the coefficient window; each thread issues a batch of loads
+  //    before writing LDS
+  for (int base = 0; base < w.nkr * w.nkc; base += 512 * kSynthCH) {
+    typename Vec<T>::V4 q[kSynthCH];
+    synth_load<T, L, BC>(d, w, base, q, abuf);
+    synth_put<T>(w, base, q, smem_raw);
+  }
+  __syncthreads();
+  synth_passes<T, L, BC>(d, f, w, smem_raw, wr);
+}
+
+// Column then row passes over the staged window (steps 2 and 3).
+template <typename T, int L, int BC, typename W>
+__device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>& f,
+                                             const SynthWin& w, unsigned char* smem_raw, W& wr) {
   constexpr int HL = L / 2;
   // extended modes shift the signal by e = L - 1 (odd): the first row of a
   // pair has odd n and the second row uses the next coefficient row
   constexpr bool SHIFT = (BC == SYM);
   using V2 = typename Vec<T>::V2;
   using V4 = typename Vec<T>::V4;
-
-  const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
+  const int Nr = d.r.N, Nc = d.c.N;
   const int er = SHIFT ? d.r.e : 0;
   const int ec = SHIFT ? d.c.e : 0;
-  int kwr, nkr, kwc, nkc;
-  synth_axis_window(r0, r1, Nr, er, L, BC, kwr, nkr);
-  synth_axis_window(c0, c1, Nc, ec, L, BC, kwc, nkc);
-
-  V4* sc = reinterpret_cast<V4*>(smem_raw);  // [nkr][nkc] (a, H, V, D)
-  V2* st = reinterpret_cast<V2*>(sc + nkr * nkc);  // [TR][nkc] (lo, hi) after the row fold
-
-  const T* A = static_cast<const T*>(d.a) + (long long)img * d.stride_a;
-  const T* HVD = static_cast<const T*>(d.hvd) + (long long)img * d.stride_hvd;
-  const long long band = (long long)Kr * Kc;
-
-  // 1. stage the coefficient window, bands interleaved; each thread issues a
-  //    batch of loads before writing LDS
-  constexpr int CH = 4;
-  for (int base = 0; base < nkr * nkc; base += 512 * CH) {
-    V4 q[CH];
-#pragma unroll
-    for (int it = 0; it < CH; ++it) {
-      const int idx = base + threadIdx.x + it * 512;
-      q[it].x = q[it].y = q[it].z = q[it].w = T(0);
-      if (idx < nkr * nkc) {
-        const int i = idx / nkc;
-        const int j = idx - i * nkc;
-        int kr = kwr + i, kc = kwc + j;
-        bool ok;
-        if (BC == PER) {
-          kr = posmod(kr, Kr);
-          kc = posmod(kc, Kc);
-          ok = true;
-        } else {
-          ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
-        }
-        if (ok) {
-          const long long off = (long long)kr * Kc + kc;
-          q[it].x = abuf ? abuf->p[(kr - abuf->r0) * abuf->pitch + (kc - abuf->c0)] : A[off];
-          q[it].y = HVD[off];
-          q[it].z = HVD[band + off];
-          q[it].w = HVD[2 * band + off];
-        }
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < CH; ++it) {
-      const int idx = base + threadIdx.x + it * 512;
-      if (idx < nkr * nkc) sc[idx] = q[it];
-    }
-  }
-  __syncthreads();
+  const int r0 = w.r0, r1 = w.r1, c0 = w.c0, c1 = w.c1;
+  const int kwr = w.kwr, nkc = w.nkc, kwc = w.kwc;
+  V4* sc = reinterpret_cast<V4*>(smem_raw);            // [nkr][nkc] (a, H, V, D)
+  V2* st = reinterpret_cast<V2*>(sc + w.nkr * w.nkc);  // [rows][nkc] (lo, hi) after the row fold
 
   // 2. column-direction synthesis. Regular row pairs (single preimage, both
   //    rows in the tile) run the paired fast path; border rows and a ragged

@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -178,7 +179,8 @@ def fista_targets(w: ops.WaveletSpec, blurs, b: torch.Tensor, lam: float, iters:
 
 
 def log(msg: str) -> None:
-    print(f"[warm-start {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+    """Progress line on stderr (stdout stays free for results)."""
+    print(f"[warm-start {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def make_pairs(w: ops.WaveletSpec, n: int, lam: float, iters: int, seed: int, device,
