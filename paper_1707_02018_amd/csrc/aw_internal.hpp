@@ -173,6 +173,12 @@ struct ProxEpi {
   double inv_L, thresh, beta;
   double* partials;  // [image][pstride]; this level's tiles at pbase + tile
   int pbase, pstride;
+  // batched plans: beta_k = beta_tab[k - 1] for the device counter k (clamped
+  // to [1, beta_len]) instead of `beta`, and per-tile sums of (x_k - x_{k-1})^2
+  const double* beta_tab;
+  const int* counter;
+  int beta_len;
+  double* dx_partials;
 };
 
 // Fold of a materialised extended image (rows.N+2e x cols.N+2e) -> out.
@@ -196,6 +202,7 @@ struct AnaItem {
   AnaLevel d;
   Taps<T> f;
   int image;
+  ProxEpi pe;  // fused FISTA update (batched plans)
 };
 
 // Item owning tile t of a batched launch: prefix[i] <= t < prefix[i+1]
@@ -307,7 +314,10 @@ hipError_t launch_synth_batch(int dtype, int L, int bc, int var, const void* ite
                               const int* prefix, int n, int total, const int* active, size_t lds,
                               hipStream_t s);
 hipError_t launch_ana_batch(int dtype, int L, int bc, int var, const void* items,
-                            const int* prefix, int n, int total, const int* active, hipStream_t s);
+                            const int* prefix, int n, int total, const int* active, hipStream_t s,
+                            bool prox = false);
+void make_ana_item_prox(const AnaLevel& d, const double* lo, int L, int image, const ProxEpi& pe,
+                        void* out);
 hipError_t launch_blur_batch(int dtype, int radius, bool adj, int var, const void* items,
                              const int* prefix, int n, int total, const int* active,
                              hipStream_t s);

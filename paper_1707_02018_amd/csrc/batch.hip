@@ -5,9 +5,11 @@
 // levels, PSF radius for the blur): descriptor items plus a prefix of tile
 // counts, uploaded once. One iteration enqueues, for every stage, one launch
 // per class over all tiles of all images of that class:
-//   W levels J..1 -> R(.) - b (+ residual partials) -> R^* -> W^* levels 1..J
-//   -> proximal/momentum update (beta_k from a device table indexed by a
-//   device iteration counter) -> per-image objective partials -> counter++.
+//   W levels J..1 -> R(.) - b (+ residual partials) -> R^* -> W^* levels 1..J,
+//   each analysis tile applying the proximal/momentum update to the
+//   coefficients it produces (beta_k from a device table indexed by a device
+//   iteration counter; per-tile partials of ||x_k||_1 and ||x_k - x_{k-1}||^2)
+//   -> per-image objective sums -> counter++.
 // Classes of one stage are independent and run on forked streams. Nothing is
 // allocated, copied or synchronised per iteration and every kernel reads its
 // varying inputs from device memory, so an iteration can be captured once into
@@ -30,62 +32,6 @@ template <typename T, bool ADJ>
 BlurArgs<T> make_blur_args(const BlurDesc& b);
 
 // ------------------------------------------------------------ device kernels
-constexpr int kBatchProxThreads = 256;
-constexpr int kBatchProxChunk = kBatchProxThreads * 16;
-
-struct ProxItem {
-  long long off;  // coefficient offset of the image
-  long long n;    // coefficients of the image
-  int image;
-};
-
-// x_k = soft(y - g / L, lambda / L); y_{k+1} = x_k + beta_k (x_k - x_{k-1});
-// per-block FP64 partials of ||x_k||_1 and ||x_k - x_{k-1}||^2.
-template <typename T>
-__global__ __launch_bounds__(kBatchProxThreads) void batch_prox_kernel(
-    const ProxItem* __restrict__ items, const int* __restrict__ prefix, int n,
-    const int* __restrict__ active, const T* __restrict__ grad, T* __restrict__ x,
-    T* __restrict__ y, double inv_L, double thresh, const double* __restrict__ beta_tab,
-    int beta_len, const int* __restrict__ counter, double* __restrict__ l1_part,
-    double* __restrict__ dx_part) {
-  __shared__ double red[2][kBatchProxThreads];
-  const int i = find_item(prefix, n, blockIdx.x);
-  const ProxItem it = items[i];
-  double l1 = 0.0, dx = 0.0;
-  if (!active || active[it.image]) {
-    int k = *counter;
-    k = k < 1 ? 1 : (k > beta_len ? beta_len : k);
-    const T beta = (T)beta_tab[k - 1];
-    const T il = (T)inv_L, th = (T)thresh;
-    const long long b0 = (long long)(blockIdx.x - prefix[i]) * kBatchProxChunk;
-    const long long e0 = b0 + kBatchProxChunk < it.n ? b0 + kBatchProxChunk : it.n;
-    for (long long j = b0 + threadIdx.x; j < e0; j += kBatchProxThreads) {
-      const long long o = it.off + j;
-      const T v = y[o] - grad[o] * il;
-      const T xn = v > th ? v - th : (v < -th ? v + th : T(0));
-      const T xo = x[o];
-      y[o] = xn + beta * (xn - xo);
-      x[o] = xn;
-      l1 += (double)(xn < T(0) ? -xn : xn);
-      dx += (double)(xn - xo) * (double)(xn - xo);
-    }
-  }
-  red[0][threadIdx.x] = l1;
-  red[1][threadIdx.x] = dx;
-  __syncthreads();
-  for (int s = kBatchProxThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    l1_part[blockIdx.x] = red[0][0];
-    dx_part[blockIdx.x] = red[1][0];
-  }
-}
-
 // obj[i] = {1/2 ||A y - b||^2, ||x||_1, ||x_k - x_{k-1}||^2}: fixed-order sums
 // over the image's tile and block ranges; inactive images keep their values.
 __global__ __launch_bounds__(256) void batch_reduce_kernel(
@@ -127,18 +73,6 @@ __global__ void batch_reset_kernel(int* counter, int* active, int n, T* x, T* y,
     x[j] = T(0);
     y[j] = T(0);
   }
-}
-
-// ------------------------------------------------------------ launchers
-hipError_t launch_batch_prox(const ProxItem* items, const int* prefix, int n, int total,
-                             const int* active, const float* grad, float* x, float* y,
-                             double inv_L, double thresh, const double* beta_tab, int beta_len,
-                             const int* counter, double* l1_part, double* dx_part,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(batch_prox_kernel<float>, dim3(total), dim3(kBatchProxThreads), 0, s, items,
-                     prefix, n, active, grad, x, y, inv_L, thresh, beta_tab, beta_len, counter,
-                     l1_part, dx_part);
-  return hipGetLastError();
 }
 
 }  // namespace aw
@@ -185,10 +119,10 @@ struct aw_batch {
   std::vector<long long> coef_off, img_off;
   int var[4] = {0, 0, 0, 4};
   // workspace layout (bytes)
-  size_t grad_off = 0, rpart_off = 0, l1_off = 0, dx_off = 0, obj_off = 0, ctr_off = 0,
-         act_off = 0, beta_off = 0, ws_total = 0;
+  size_t rpart_off = 0, l1_off = 0, dx_off = 0, obj_off = 0, ctr_off = 0, act_off = 0,
+         beta_off = 0, ws_total = 0;
   std::vector<int> r_off;   // per-image first residual-partial slot (n + 1)
-  std::vector<int> blk_off; // per-image first prox block (n + 1)
+  std::vector<int> blk_off; // per-image first analysis-tile partial slot (n + 1)
   // bound state
   bool bound = false;
   const void* b_obs = nullptr;
@@ -197,8 +131,7 @@ struct aw_batch {
   char* ws = nullptr;
   double lambda = 0, Lstep = 1;
   std::vector<Stage> stages;
-  std::vector<aw::ProxItem> prox_items;
-  size_t prox_items_dev = 0, prox_prefix_dev = 0, rpref_dev = 0, bpref_dev = 0;
+  size_t rpref_dev = 0, bpref_dev = 0;
   char* blob = nullptr;
   hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> events;
@@ -272,15 +205,19 @@ void layout(aw_batch* p) {
     im.res_off = off;
     off = alignb(off + (size_t)im.npix * ts);
   }
-  p->grad_off = off;
-  off = alignb(off + (size_t)p->coef_off[p->n] * ts);
   p->r_off.assign(p->n + 1, 0);
   p->blk_off.assign(p->n + 1, 0);
+  int amax = 0;  // analysis-tile partial slots for either tile variant
   for (int i = 0; i < p->n; ++i) {
     int tx;
     p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
-    p->blk_off[i + 1] =
-        p->blk_off[i] + (int)((p->img[i].ncoef + aw::kBatchProxChunk - 1) / aw::kBatchProxChunk);
+    const Image& im = p->img[i];
+    for (int j = 1; j <= im.J; ++j) {
+      aw::AnaLevel d{};
+      d.r = {im.sr[j - 1], im.sr[j], im.e};
+      d.c = {im.sc[j - 1], im.sc[j], im.e};
+      amax += std::max(aw::ana_tiles(0, 0, d), aw::ana_tiles(0, 1, d));
+    }
   }
   // partial slots sized for the larger blur variant so the layout does not
   // depend on the tile configuration
@@ -292,9 +229,9 @@ void layout(aw_batch* p) {
   p->rpart_off = off;
   off = alignb(off + (size_t)rmax * sizeof(double));
   p->l1_off = off;
-  off = alignb(off + (size_t)p->blk_off[p->n] * sizeof(double));
+  off = alignb(off + (size_t)amax * sizeof(double));
   p->dx_off = off;
-  off = alignb(off + (size_t)p->blk_off[p->n] * sizeof(double));
+  off = alignb(off + (size_t)amax * sizeof(double));
   p->obj_off = off;
   off = alignb(off + (size_t)p->n * 3 * sizeof(double));
   p->ctr_off = off;
@@ -331,15 +268,27 @@ aw_status build(aw_batch* p) {
   int Jmax = 0;
   for (const Image& im : p->img) Jmax = std::max(Jmax, im.J);
   char* ws = p->ws;
-  float* grad = reinterpret_cast<float*>(ws + p->grad_off);
   double* rpart = reinterpret_cast<double*>(ws + p->rpart_off);
   // recompute residual-partial offsets for the current blur variant
   for (int i = 0; i < p->n; ++i) {
     int tx;
     p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
   }
+  // analysis-tile partial slots for the current analysis variant
+  for (int i = 0; i < p->n; ++i) {
+    const Image& im = p->img[i];
+    int t = 0;
+    for (int j = 1; j <= im.J; ++j) {
+      aw::AnaLevel d{};
+      d.r = {im.sr[j - 1], im.sr[j], im.e};
+      d.c = {im.sc[j - 1], im.sc[j], im.e};
+      t += aw::ana_tiles(0, p->var[1], d);
+    }
+    p->blk_off[i + 1] = p->blk_off[i] + t;
+  }
   std::vector<unsigned char> buf(std::max({aw::synth_item_size(0), aw::ana_item_size(0),
                                            aw::blur_item_size(0)}));
+  std::vector<int> lvl_base(p->blk_off.begin(), p->blk_off.end() - 1);
   // synthesis levels Jmax .. 1
   for (int j = Jmax; j >= 1; --j) {
     Stage st;
@@ -385,37 +334,49 @@ aw_status build(aw_batch* p) {
     }
     p->stages.push_back(std::move(st));
   }
-  // analysis levels 1 .. Jmax (W^*: weights 1/mult)
+  // analysis levels 1 .. Jmax (W^*: weights 1/mult), each tile applying the
+  // FISTA update to the coefficients it produces
   for (int j = 1; j <= Jmax; ++j) {
     Stage st;
     for (int i = 0; i < p->n; ++i) {
       const Image& im = p->img[i];
       if (im.J < j) continue;
-      float* gi = grad + p->coef_off[i];
+      float* xi = static_cast<float*>(p->x) + p->coef_off[i];
+      float* yi = static_cast<float*>(p->y) + p->coef_off[i];
       aw::AnaLevel d{};
       d.in = (j == 1) ? (const void*)(ws + im.tmp_off) : (const void*)(ws + im.a_off[j - 1]);
       d.stride_in = 0;
-      d.a = (j == im.J) ? (void*)gi : (void*)(ws + im.a_off[j]);
+      d.a = (j == im.J) ? nullptr : (void*)(ws + im.a_off[j]);
       d.stride_a = 0;
-      d.hvd = gi + im.off_hvd[j];
+      d.hvd = nullptr;
       d.stride_hvd = 0;
       d.r = {im.sr[j - 1], im.sr[j], im.e};
       d.c = {im.sc[j - 1], im.sc[j], im.e};
       d.bc = im.bc;
       d.pinv = 1;
-      aw::make_ana_item(0, d, im.w.lo, im.L, i, buf.data());
+      aw::ProxEpi pe{};
+      pe.x_hvd = xi + im.off_hvd[j];
+      pe.y_hvd = yi + im.off_hvd[j];
+      pe.x_a = (j == im.J) ? (void*)xi : nullptr;
+      pe.y_a = (j == im.J) ? (void*)yi : nullptr;
+      pe.inv_L = 1.0 / p->Lstep;
+      pe.thresh = p->lambda / p->Lstep;
+      pe.partials = reinterpret_cast<double*>(ws + p->l1_off);
+      pe.dx_partials = reinterpret_cast<double*>(ws + p->dx_off);
+      pe.pbase = lvl_base[i];
+      pe.pstride = 0;
+      pe.beta_tab = reinterpret_cast<const double*>(ws + p->beta_off);
+      pe.counter = reinterpret_cast<const int*>(ws + p->ctr_off);
+      pe.beta_len = kBetaLen;
+      const int tiles = aw::ana_tiles(0, p->var[1], d);
+      lvl_base[i] += tiles;
+      aw::make_ana_item_prox(d, im.w.lo, im.L, i, pe, buf.data());
       Group& g = group_for(st, 1, im.L, im.bc);
-      add_item(g, buf.data(), aw::ana_item_size(0), aw::ana_tiles(0, p->var[1], d));
+      add_item(g, buf.data(), aw::ana_item_size(0), tiles);
     }
     p->stages.push_back(std::move(st));
   }
-  // device blob: all groups' items and prefixes, prox items and prefixes
-  p->prox_items.clear();
-  std::vector<int> prox_prefix(1, 0);
-  for (int i = 0; i < p->n; ++i) {
-    p->prox_items.push_back(aw::ProxItem{p->coef_off[i], p->img[i].ncoef, i});
-    prox_prefix.push_back(p->blk_off[i + 1]);
-  }
+  // device blob: all groups' items and prefixes, partial-slot prefixes
   size_t off = 0;
   for (Stage& st : p->stages)
     for (Group& g : st.groups) {
@@ -424,10 +385,6 @@ aw_status build(aw_batch* p) {
       g.prefix_dev = off;
       off = alignb(off + g.prefix.size() * sizeof(int));
     }
-  p->prox_items_dev = off;
-  off = alignb(off + p->prox_items.size() * sizeof(aw::ProxItem));
-  p->prox_prefix_dev = off;
-  off = alignb(off + prox_prefix.size() * sizeof(int));
   p->rpref_dev = off;
   off = alignb(off + p->r_off.size() * sizeof(int));
   p->bpref_dev = off;
@@ -441,9 +398,6 @@ aw_status build(aw_batch* p) {
       std::copy(g.items.begin(), g.items.end(), host.begin() + g.items_dev);
       std::memcpy(host.data() + g.prefix_dev, g.prefix.data(), g.prefix.size() * sizeof(int));
     }
-  std::memcpy(host.data() + p->prox_items_dev, p->prox_items.data(),
-              p->prox_items.size() * sizeof(aw::ProxItem));
-  std::memcpy(host.data() + p->prox_prefix_dev, prox_prefix.data(), prox_prefix.size() * sizeof(int));
   std::memcpy(host.data() + p->rpref_dev, p->r_off.data(), p->r_off.size() * sizeof(int));
   std::memcpy(host.data() + p->bpref_dev, p->blk_off.data(), p->blk_off.size() * sizeof(int));
   if (hipMemcpy(p->blob, host.data(), off, hipMemcpyHostToDevice) != hipSuccess)
@@ -472,7 +426,8 @@ aw_status launch_group(aw_batch* p, const Group& g, hipStream_t s) {
                                  g.lds, s);
       break;
     case 1:
-      e = aw::launch_ana_batch(0, g.key0, g.key1, p->var[1], items, prefix, g.n, g.total, active, s);
+      e = aw::launch_ana_batch(0, g.key0, g.key1, p->var[1], items, prefix, g.n, g.total, active, s,
+                               true);
       break;
     default:
       e = aw::launch_blur_batch(0, g.key0, g.kind == 3, p->var[2], items, prefix, g.n, g.total,
@@ -615,16 +570,6 @@ aw_status aw_batch_step(aw_batch* p, void* stream) {
     }
   }
   char* ws = p->ws;
-  const int total_blocks = p->blk_off[p->n];
-  hipError_t e = aw::launch_batch_prox(
-      reinterpret_cast<const aw::ProxItem*>(p->blob + p->prox_items_dev),
-      reinterpret_cast<const int*>(p->blob + p->prox_prefix_dev), p->n, total_blocks,
-      reinterpret_cast<const int*>(ws + p->act_off), reinterpret_cast<const float*>(ws + p->grad_off),
-      static_cast<float*>(p->x), static_cast<float*>(p->y), 1.0 / p->Lstep, p->lambda / p->Lstep,
-      reinterpret_cast<const double*>(ws + p->beta_off), kBetaLen,
-      reinterpret_cast<const int*>(ws + p->ctr_off), reinterpret_cast<double*>(ws + p->l1_off),
-      reinterpret_cast<double*>(ws + p->dx_off), s);
-  if (e != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(e));
   hipLaunchKernelGGL(aw::batch_reduce_kernel, dim3(p->n), dim3(256), 0, s, p->n,
                      reinterpret_cast<const int*>(p->blob + p->rpref_dev),
                      reinterpret_cast<const double*>(ws + p->rpart_off),
@@ -635,7 +580,7 @@ aw_status aw_batch_step(aw_batch* p, void* stream) {
                      reinterpret_cast<double*>(ws + p->obj_off));
   hipLaunchKernelGGL(aw::batch_counter_kernel, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<int*>(ws + p->ctr_off));
-  e = hipGetLastError();
+  const hipError_t e = hipGetLastError();
   return e == hipSuccess ? AW_OK : bfail(AW_EHIP, hipGetErrorString(e));
 }
 

@@ -440,7 +440,17 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
   T* HVD = static_cast<T*>(d.hvd) + (long long)img * d.stride_hvd;
   const long long band = (long long)Kr * Kc;
   const int kc = kc0 + kk;
-  double l1 = 0.0;
+  double l1 = 0.0, dx = 0.0;
+  T beta = T(0);
+  if constexpr (PROX) {
+    if (pe.beta_tab) {
+      int k = *pe.counter;
+      k = k < 1 ? 1 : (k > pe.beta_len ? pe.beta_len : k);
+      beta = (T)pe.beta_tab[k - 1];
+    } else {
+      beta = (T)pe.beta;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < KB; ++r) {
     T a = T(0), H = T(0), V = T(0), D = T(0);
@@ -458,7 +468,7 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
       if constexpr (PROX) {
         const T g[4] = {a, H, V, D};
         T xn[4];
-        const T il = (T)pe.inv_L, th = (T)pe.thresh, be = (T)pe.beta;
+        const T il = (T)pe.inv_L, th = (T)pe.thresh, be = beta;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const T v = py[r][q] - g[q] * il;
@@ -471,12 +481,14 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
           Yh[(q - 1) * band] = xn[q] + be * (xn[q] - px[r][q]);
           Xh[(q - 1) * band] = xn[q];
           l1 += (double)(xn[q] < T(0) ? -xn[q] : xn[q]);
+          dx += (double)(xn[q] - px[r][q]) * (double)(xn[q] - px[r][q]);
         }
         if (pe.x_a) {
           const long long oa = (long long)img * d.stride_a + off;
           static_cast<T*>(pe.y_a)[oa] = xn[0] + be * (xn[0] - px[r][0]);
           static_cast<T*>(pe.x_a)[oa] = xn[0];
           l1 += (double)(xn[0] < T(0) ? -xn[0] : xn[0]);
+          dx += (double)(xn[0] - px[r][0]) * (double)(xn[0] - px[r][0]);
         } else {
           Aout[off] = a;
         }
@@ -489,17 +501,23 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
     }
   }
   if constexpr (PROX) {
-    if (pe.partials) {  // fixed-order tile sum of |x_k|
-      __shared__ double red[NT];
-      red[threadIdx.x] = l1;
+    if (pe.partials) {  // fixed-order tile sums of |x_k| (and (x_k - x_{k-1})^2)
+      __shared__ double red[2][NT];
+      red[0][threadIdx.x] = l1;
+      red[1][threadIdx.x] = dx;
       __syncthreads();
       for (int w = NT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if (threadIdx.x < w) {
+          red[0][threadIdx.x] += red[0][threadIdx.x + w];
+          red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
         __syncthreads();
       }
       if (threadIdx.x == 0) {
         const int gx = (Kc + TKC - 1) / TKC;
-        pe.partials[(long long)img * pe.pstride + pe.pbase + by * gx + bx] = red[0];
+        const long long slot = (long long)img * pe.pstride + pe.pbase + by * gx + bx;
+        pe.partials[slot] = red[0][0];
+        if (pe.dx_partials) pe.dx_partials[slot] = red[1][0];
       }
     }
   }
@@ -530,7 +548,7 @@ static int ana_variant(int dtype, const AnaLevel& d, int batch) {
   return tiles < 1024 ? 1 : 0;
 }
 
-template <typename T, int L, int BC, int VAR>
+template <typename T, int L, int BC, int VAR, bool PROX = false>
 __global__ __launch_bounds__(512) void ana_batch_kernel(
     const AnaItem<T>* __restrict__ items, const int* __restrict__ prefix, int n,
     const int* __restrict__ active) {
@@ -540,7 +558,10 @@ __global__ __launch_bounds__(512) void ana_batch_kernel(
   if (active && !active[it.image]) return;
   const int t = b - prefix[i];
   const int tx = (it.d.c.K + AnaTile<T, VAR>::TKC - 1) / AnaTile<T, VAR>::TKC;
-  ana_tile<T, L, BC, VAR>(it.d, it.f, t % tx, t / tx, 0);
+  if constexpr (PROX)
+    ana_tile<T, L, BC, VAR, true>(it.d, it.f, t % tx, t / tx, 0, it.pe);
+  else
+    ana_tile<T, L, BC, VAR>(it.d, it.f, t % tx, t / tx, 0);
 }
 
 template <typename T, int L, int BC, int VAR>
@@ -680,6 +701,12 @@ void make_synth_item(int dtype, const SynthLevel& d, const double* lo, int L, in
     *static_cast<SynthItem<float>*>(out) = it;
   }
 }
+void make_ana_item_prox(const AnaLevel& d, const double* lo, int L, int image, const ProxEpi& pe,
+                        void* out) {
+  AnaItem<float> it{d, make_taps<float>(lo, L), image, pe};
+  *static_cast<AnaItem<float>*>(out) = it;
+}
+
 void make_ana_item(int dtype, const AnaLevel& d, const double* lo, int L, int image, void* out) {
   if (dtype) {
     AnaItem<double> it{d, make_taps<double>(lo, L), image};
@@ -706,9 +733,13 @@ static hipError_t launch_synth_batch_t(const void* items, const int* prefix, int
 
 template <typename T, int L, int BC, int V>
 static hipError_t launch_ana_batch_t(const void* items, const int* prefix, int n, int total,
-                                     const int* active, hipStream_t s) {
-  hipLaunchKernelGGL((ana_batch_kernel<T, L, BC, V>), dim3(total), dim3(512), 0, s,
-                     static_cast<const AnaItem<T>*>(items), prefix, n, active);
+                                     const int* active, hipStream_t s, bool prox) {
+  if (prox)
+    hipLaunchKernelGGL((ana_batch_kernel<T, L, BC, V, true>), dim3(total), dim3(512), 0, s,
+                       static_cast<const AnaItem<T>*>(items), prefix, n, active);
+  else
+    hipLaunchKernelGGL((ana_batch_kernel<T, L, BC, V>), dim3(total), dim3(512), 0, s,
+                       static_cast<const AnaItem<T>*>(items), prefix, n, active);
   return hipGetLastError();
 }
 
@@ -744,8 +775,8 @@ hipError_t launch_synth_batch(int dtype, int L, int bc, int var, const void* ite
 }
 hipError_t launch_ana_batch(int dtype, int L, int bc, int var, const void* items,
                             const int* prefix, int n, int total, const int* active,
-                            hipStream_t s) {
-  AW_BATCH_DISPATCH(launch_ana_batch_t, items, prefix, n, total, active, s)
+                            hipStream_t s, bool prox) {
+  AW_BATCH_DISPATCH(launch_ana_batch_t, items, prefix, n, total, active, s, prox)
 }
 #undef AW_BATCH_DISPATCH
 
