@@ -274,11 +274,7 @@ hipError_t launch_blur_adjoint(int dtype, const BlurDesc& b, int batch, const vo
                                hipStream_t s);
 int blur_tiles(int dtype, const BlurDesc& b);
 
-// FISTA proximal/momentum update over n coefficients per image (in place on
-// x, y), optional per-block l1 partials [image][block]. Returns blocks/image.
-hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad, void* x, void* y,
-                             double inv_L, double thresh, double beta, double* partials,
-                             hipStream_t s);
+// Blocks per image of launch_l1_partials over n coefficients.
 int fista_prox_blocks(long long n);
 // Chained synthesis (FP32, zpd / sym without the two-step fold): fills the
 // chain's LDS plan and returns its dynamic LDS bytes (0: not supported).

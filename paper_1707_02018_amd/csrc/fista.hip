@@ -1,11 +1,8 @@
-// FISTA proximal / momentum update and deterministic reductions (gfx950).
-//
-// With the gradient g = A^*(A y_k - b) already in memory, one pass computes
-//   x_k     = soft(y_k - g / L, lambda / L)
-//   y_{k+1} = x_k + beta_k (x_k - x_{k-1})
-// in place (x holds x_{k-1} on entry), plus per-block FP64 partials of
-// ||x_k||_1. Reductions are two-stage with a fixed summation order, so the
-// objective is bitwise reproducible run to run.
+// FISTA reductions (gfx950): per-block FP64 partials of ||x||_1 for the exact
+// objective, the objective's final combination, and fixed-order partial sums,
+// so every objective is bitwise reproducible run to run. The proximal /
+// momentum update itself runs in the analysis kernels' epilogue
+// (wavelet.hip, ana_tile with PROX).
 #include "aw_internal.hpp"
 
 namespace aw {
@@ -18,53 +15,6 @@ int fista_prox_blocks(long long n) {
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   return (int)b;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kProxThreads) void prox_kernel(long long n, const T* __restrict__ grad,
-                                                            T* __restrict__ x, T* __restrict__ y,
-                                                            T inv_L, T thresh, T beta,
-                                                            double* __restrict__ partials) {
-  __shared__ double red[kProxThreads];
-  const long long base = (long long)blockIdx.y * n;
-  const T* G = grad + base;
-  T* X = x + base;
-  T* Y = y + base;
-  double l1 = 0.0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const T v = Y[i] - G[i] * inv_L;
-    const T xn = v > thresh ? v - thresh : (v < -thresh ? v + thresh : T(0));
-    const T xo = X[i];
-    Y[i] = xn + beta * (xn - xo);
-    X[i] = xn;
-    l1 += (double)(xn < T(0) ? -xn : xn);
-  }
-  if (partials) {
-    red[threadIdx.x] = l1;
-    __syncthreads();
-    for (int s = kProxThreads / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
-  }
-}
-
-hipError_t launch_fista_prox(int dtype, int batch, long long n, const void* grad, void* x, void* y,
-                             double inv_L, double thresh, double beta, double* partials,
-                             hipStream_t s) {
-  dim3 grid(fista_prox_blocks(n), batch);
-  if (dtype)
-    hipLaunchKernelGGL(prox_kernel<double>, grid, dim3(kProxThreads), 0, s, n,
-                       static_cast<const double*>(grad), static_cast<double*>(x),
-                       static_cast<double*>(y), inv_L, thresh, beta, partials);
-  else
-    hipLaunchKernelGGL(prox_kernel<float>, grid, dim3(kProxThreads), 0, s, n,
-                       static_cast<const float*>(grad), static_cast<float*>(x),
-                       static_cast<float*>(y), (float)inv_L, (float)thresh, (float)beta,
-                       partials);
-  return hipGetLastError();
 }
 
 template <typename T>
