@@ -259,6 +259,21 @@ def bench_warm(torch, ops, n_images: int) -> dict:
     return s
 
 
+def bench_adjoint_study() -> dict:
+    """True adjoint W^* against W^dagger in the FISTA gradient, the paper's
+    setting (three-level transform, sym, lambda = 2e-5, 2500 iterations) on a
+    256^2 synthetic image: relative error, nonzero share and SSIM at the end."""
+    from paper_1707_02018_amd import adjoint_study
+
+    out = {}
+    for taps, name in ((2, "haar_J3_sym"), (8, "db4_J3_sym")):
+        r = adjoint_study.run(256, 256, taps, 3, "sym", 2.0, 4, 2e-5, 2500, every=500)
+        out[name] = {"blurred": {k: round(v, 6) for k, v in r["blurred"].items()},
+                     **{g: {k: round(r[g][k], 6) for k in ("rel_err", "nonzero_pct", "ssim")}
+                        for g in ("adjoint", "pinv")}}
+    return out
+
+
 def cpu_baseline(size: int, bc: str, iters: int = 2) -> dict:
     """The FP64 NumPy oracle timed on this host (separate process), a bounded
     sample of the same workload: `iters` FISTA iterations at full size."""
@@ -358,6 +373,8 @@ def main():
             "R": lambda: lib.blur(bsp.c, 0, 1, P(y), P(out_img), sp),
             "R*": lambda: lib.blur_adjoint(bsp.c, 0, 1, P(y), P(out_img), sp),
             "A": lambda: lib.aw_apply_A(w.c, bsp.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
+            "A-b_fused": lambda: lib.aw_apply_A_fused(w.c, bsp.c, 0, 1, P(x), P(y), P(out_img),
+                                                      P(ws), wsn, sp),
             "A*": lambda: lib.aw_apply_A_adjoint(w.c, bsp.c, 0, 1, P(y), P(out_coef), P(ws), wsn,
                                                  sp),
             "W*_level1": lambda: lib.wavelet_synth_adjoint(w1.c, 0, 1, P(y), P(out_coef), P(ws),
@@ -437,6 +454,8 @@ def main():
         torch.cuda.empty_cache()
         log("warm start (512^2)")
         extras["warm_start"] = bench_warm(torch, ops, args.warm_images)
+        log("adjoint vs pseudoinverse gradient (256^2, 2500 iterations)")
+        extras["adjoint_vs_pinv"] = bench_adjoint_study()
     log("cpu baseline")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(N, args.bc)

@@ -158,6 +158,21 @@ aw_status aw_apply_A(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
                      const void* coef, void* img, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* img = A coef - b_obs (b_obs NULL: img = A coef), the residual of eq. (1),
+ * with the finest synthesis level and the blur in one tile pass: each tile
+ * synthesises the part of W coef its blur window reaches straight into LDS, so
+ * the full-resolution W coef never reaches memory (coarser levels run as in
+ * aw_apply_A). Bitwise equal to aw_apply_A (minus b_obs). Float32 only;
+ * boundaries zpd, sym or per; filter length 2, 8 or 16; rows and cols at least
+ * radius + 1 (and at least L - 1 for sym). Other requests return
+ * AW_EUNSUPPORTED. Same workspace as aw_apply_A. aw_apply_A is the faster of
+ * the two on gfx950 (the window's halo is synthesised by every tile that
+ * reads it and the larger LDS footprint lowers occupancy); this entry point
+ * offers the pass that writes no intermediate image. */
+aw_status aw_apply_A_fused(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                           const void* coef, const void* b_obs, void* img, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
 /* coef = A^* img = W^* R^* img (the gradient map of Sec. "Example 1"). */
 aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype,
                              int32_t batch, const void* img, void* coef, void* workspace,
@@ -173,7 +188,14 @@ aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dty
  *   obj    device doubles [batch][2] or NULL: written when want_objective:
  *          obj[2i] = 1/2 ||A y_k - b||^2, obj[2i+1] = ||x_k||_1
  *   k      iteration index (>= 1), incremented by fista_step
- *   t      t_k (t_1 = 1), replaced by t_{k+1} by fista_step            */
+ *   t      t_k (t_1 = 1), replaced by t_{k+1} by fista_step
+ *   gradient  AW_GRAD_ADJOINT (0, the zero-initialised default): the
+ *          gradient W^* R^* (A y - b) with the true adjoint; AW_GRAD_PINV: W^dagger in
+ *          the place of W^*, the approximation that Sec. "The adjoint for
+ *          orthogonal wavelets" compares with the true adjoint (the two coincide
+ *          for zpd and per). Other values: AW_EINVAL.                       */
+typedef enum { AW_GRAD_ADJOINT = 0, AW_GRAD_PINV = 1 } aw_gradient_map;
+
 typedef struct {
   void* x;
   void* y;
@@ -181,6 +203,7 @@ typedef struct {
   double* obj;
   int64_t k;
   double t;
+  int32_t gradient;
 } aw_fista_state;
 
 /* One FISTA iteration with constant step 1/L:

@@ -33,7 +33,8 @@ class Blur(ctypes.Structure):
 
 class FistaState(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("resid", ctypes.c_void_p),
-                ("obj", ctypes.c_void_p), ("k", ctypes.c_int64), ("t", ctypes.c_double)]
+                ("obj", ctypes.c_void_p), ("k", ctypes.c_int64), ("t", ctypes.c_double),
+                ("gradient", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -54,6 +55,7 @@ SIGNATURES = {
     "blur": [_B, _i32, _i32, _P, _P, _P],
     "blur_adjoint": [_B, _i32, _i32, _P, _P, _P],
     "aw_apply_A": [_W, _B, _i32, _i32, _P, _P, _P, _sz, _P],
+    "aw_apply_A_fused": [_W, _B, _i32, _i32, _P, _P, _P, _P, _sz, _P],
     "aw_apply_A_adjoint": [_W, _B, _i32, _i32, _P, _P, _P, _sz, _P],
     "fista_step": [_W, _B, _i32, _i32, _P, _dbl, _dbl, ctypes.POINTER(FistaState), _i32, _P, _sz,
                    _P],

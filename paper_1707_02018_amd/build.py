@@ -19,7 +19,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libadjwave.so")
-SOURCES = ["api.hip", "wavelet.hip", "blur.hip", "fista.hip", "conv.hip", "batch.hip", "cnn.hip"]
+SOURCES = ["api.hip", "wavelet.hip", "blur.hip", "fista.hip", "conv.hip", "batch.hip", "cnn.hip",
+           "fused.hip"]
 HEADERS = ["aw_internal.hpp", os.path.join("..", "..", "include", "adjwave.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

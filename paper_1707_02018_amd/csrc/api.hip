@@ -297,7 +297,7 @@ aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* im
 // every level's epilogue: x, y updated in place, l1 partials per tile.
 aw_status run_analysis_prox(const WavePlan& p, aw_dtype dt, int batch, const void* img, void* x,
                             void* y, void* ws, const WsLayout& l, double inv_L, double thresh,
-                            double beta, double* partials, hipStream_t s) {
+                            double beta, double* partials, int pinv, hipStream_t s) {
   const size_t ts = dsize(dt);
   int pbase = 0;
   for (int j = 1; j <= p.J; ++j) {
@@ -311,7 +311,7 @@ aw_status run_analysis_prox(const WavePlan& p, aw_dtype dt, int batch, const voi
     d.r = {p.sr[j - 1], p.sr[j], p.e};
     d.c = {p.sc[j - 1], p.sc[j], p.e};
     d.bc = p.bc;
-    d.pinv = 1;
+    d.pinv = pinv;
     aw::ProxEpi pe{};
     pe.x_hvd = static_cast<char*>(x) + p.off_hvd[j] * ts;
     pe.y_hvd = static_cast<char*>(y) + p.off_hvd[j] * ts;
@@ -560,6 +560,27 @@ aw_status aw_apply_A(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   return st == AW_OK ? ok() : st;
 }
 
+aw_status aw_apply_A_fused(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                           const void* coef, const void* b_obs, void* img, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = op_common(w, b, dtype, batch, coef, img, workspace, workspace_bytes, p, d, l);
+  if (st != AW_OK) return st;
+  if (dtype != AW_F32) return fail(AW_EUNSUPPORTED, "fused A runs in float32 only");
+  const aw::SynthLevel d1 = synth_desc(p, dtype, coef, img, workspace, l, 1, 1);
+  if (!aw::synth_blur_supported(p.L, d1, d))
+    return fail(AW_EUNSUPPORTED,
+                "fused A needs zpd/sym/per, filter length 2, 8 or 16, an image of at least "
+                "radius + 1 (and, for sym, L - 1) samples per axis and a window within LDS");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = run_synthesis(p, dtype, batch, coef, img, workspace, l, 1, s, 2)) != AW_OK) return st;
+  st = hip_check(aw::launch_synth_blur(p.L, p.lo, d1, d, b_obs, img, batch, s),
+                 "fused synthesis-blur launch");
+  return st == AW_OK ? ok() : st;
+}
+
 aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
                              const void* img, void* coef, void* workspace, size_t workspace_bytes,
                              void* stream) {
@@ -593,6 +614,8 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
   if (state->k < 1) return fail(AW_EINVAL, "k=%lld (iterations count from 1)", (long long)state->k);
   if (!(state->t >= 1.0)) return fail(AW_EINVAL, "t=%g (t_1 = 1, increasing)", state->t);
+  if (state->gradient != AW_GRAD_ADJOINT && state->gradient != AW_GRAD_PINV)
+    return fail(AW_EINVAL, "gradient=%d (AW_GRAD_ADJOINT or AW_GRAD_PINV)", (int)state->gradient);
   const bool obj = want_objective && state->obj;
   hipStream_t s = (hipStream_t)stream;
   const int dtype_i = dtype == AW_F64;
@@ -614,8 +637,11 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   const double t = state->t;
   const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
   const double beta = (t - 1.0) / tn;
+  // the true adjoint folds with the 1/mult weights of (E^dagger)^*; W^dagger
+  // extends with weight one
+  const int fold_w = state->gradient == AW_GRAD_PINV ? 0 : 1;
   if ((st = run_analysis_prox(p, dtype, batch, img, state->x, state->y, workspace, l, 1.0 / L,
-                              lambda / L, beta, obj ? pl : nullptr, s)) != AW_OK)
+                              lambda / L, beta, obj ? pl : nullptr, fold_w, s)) != AW_OK)
     return st;
   if (obj) {
     if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, state->obj, 2, 0, s),

@@ -278,6 +278,11 @@ int blur_tiles(int dtype, const BlurDesc& b);
 int fista_prox_blocks(long long n);
 // Chained synthesis (FP32, zpd / sym without the two-step fold): fills the
 // chain's LDS plan and returns its dynamic LDS bytes (0: not supported).
+// A = R W with the finest synthesis level and the blur in one tile pass
+// (FP32, zpd / sym / per, filter lengths 2, 8, 16); sub = b or NULL.
+bool synth_blur_supported(int L, const SynthLevel& d, const BlurDesc& b);
+hipError_t launch_synth_blur(int L, const double* lo, const SynthLevel& d, const BlurDesc& b,
+                             const void* sub, void* y, int batch, hipStream_t s);
 size_t synth_chain_plan(int dtype, int L, SynthChain& c);
 hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size_t lds, int batch,
                               hipStream_t s);

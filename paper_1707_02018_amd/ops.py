@@ -229,6 +229,27 @@ def apply_A(w: WaveletSpec, b: BlurSpec, coef: torch.Tensor, out=None) -> torch.
     return out
 
 
+def apply_A_fused(w: WaveletSpec, b: BlurSpec, coef: torch.Tensor, sub=None,
+                  out=None) -> torch.Tensor:
+    """A coef - sub (sub None: A coef) with the finest synthesis level and the
+    blur in one pass (float32; zpd, sym or per; 2, 8 or 16 taps)."""
+    _dev(coef)
+    batch = _batch_coef(coef, w.ncoef)
+    shape = coef.shape[:-1] + (w.rows, w.cols)
+    if sub is not None:
+        _dev(sub)
+        if tuple(sub.shape) != tuple(shape) or sub.dtype != coef.dtype or not sub.is_contiguous():
+            raise ValueError(f"sub must be a contiguous {coef.dtype} tensor of shape {tuple(shape)}")
+    if out is None:
+        out = torch.empty(shape, dtype=coef.dtype, device=coef.device)
+    ws, n = _workspace(w, b, coef, batch)
+    check("aw_apply_A_fused",
+          load().aw_apply_A_fused(w.c, b.c, _dtype_code(coef), batch, _ptr(coef),
+                                  _ptr(sub) if sub is not None else None, _ptr(_dev(out)),
+                                  _ptr(ws), n, _stream(coef)))
+    return out
+
+
 def apply_A_adjoint(w: WaveletSpec, b: BlurSpec, img: torch.Tensor, out=None) -> torch.Tensor:
     _dev(img)
     batch = _batch_img(img, w.rows, w.cols)
@@ -246,8 +267,16 @@ class FistaState:
     """Device buffers and counters of one FISTA run (x, y coefficient
     tensors, residual image, objective partials)."""
 
-    def __init__(self, w: WaveletSpec, b: BlurSpec, b_obs: torch.Tensor, x0=None):
+    GRADIENTS = {"adjoint": 0, "pinv": 1}
+
+    def __init__(self, w: WaveletSpec, b: BlurSpec, b_obs: torch.Tensor, x0=None,
+                 gradient: str = "adjoint"):
+        """gradient: "adjoint" (W^* R^*, the true gradient) or "pinv" (W^dagger in
+        the place of W^*)."""
         _dev(b_obs)
+        if gradient not in self.GRADIENTS:
+            raise ValueError(f"gradient must be one of {sorted(self.GRADIENTS)}")
+        self.gradient = gradient
         self.w, self.b = w, b
         self.batch = _batch_img(b_obs, w.rows, w.cols)
         lead = b_obs.shape[:-2]
@@ -265,6 +294,7 @@ class FistaState:
         s.x, s.y, s.resid = self.x.data_ptr(), self.y.data_ptr(), self.resid.data_ptr()
         s.obj = self.obj.data_ptr()
         s.k, s.t = self.k, self.t
+        s.gradient = self.GRADIENTS[self.gradient]
         return s
 
 
