@@ -14,6 +14,11 @@ Sec. "The adjoint for orthogonal wavelets"):
 
 The step bound L = 1 follows from ||R|| = 1 and ||W|| = 1 (a reading: the
 paper leaves L unstated). The l1 norm covers every coefficient.
+
+The gradient map is W^* R^* by default (gradient="adjoint"). gradient="pinv"
+puts W^dagger in the place of W^*, the approximation the paper compares with
+the true adjoint in Sec. "The adjoint for orthogonal wavelets" (identical for
+zpd and per, where W^* = W^dagger).
 """
 from __future__ import annotations
 
@@ -39,6 +44,10 @@ class Problem:
     def A_adj(self, img):
         return wv.W_adj(bl.R_adj(img, self.taps), self.h, self.mode, self.levels)
 
+    def A_adj_pinv(self, img):
+        """W^dagger R^* img: the adjoint of W replaced by its left inverse."""
+        return wv.W_pinv(bl.R_adj(img, self.taps), self.h, self.mode, self.levels)
+
 
 def soft(v: np.ndarray, tau: float) -> np.ndarray:
     return np.sign(v) * np.maximum(np.abs(v) - tau, 0.0)
@@ -49,8 +58,13 @@ def objective(prob: Problem, x, b, lam: float) -> float:
     return 0.5 * float(np.sum(r * r)) + lam * float(np.sum(np.abs(x)))
 
 
-def grad(prob: Problem, x, b):
-    return prob.A_adj(prob.A(x) - b)
+def grad(prob: Problem, x, b, gradient: str = "adjoint"):
+    r = prob.A(x) - b
+    if gradient == "adjoint":
+        return prob.A_adj(r)
+    if gradient == "pinv":
+        return prob.A_adj_pinv(r)
+    raise ValueError(f"gradient={gradient!r}")
 
 
 def t_next(t: float) -> float:
@@ -65,23 +79,24 @@ def momentum(k: int) -> float:
     return (t - 1.0) / t_next(t)
 
 
-def fista_step(prob: Problem, x_prev, y, b, beta: float, lam: float, L: float = 1.0):
+def fista_step(prob: Problem, x_prev, y, b, beta: float, lam: float, L: float = 1.0,
+               gradient: str = "adjoint"):
     """One iteration: x_k = soft(y_k - grad f(y_k)/L, lambda/L) and
     y_{k+1} = x_k + beta_k (x_k - x_{k-1}); returns (x_k, y_{k+1})."""
-    x = soft(y - grad(prob, y, b) / L, lam / L)
+    x = soft(y - grad(prob, y, b, gradient) / L, lam / L)
     y_next = x + beta * (x - x_prev)
     return x, y_next
 
 
 def fista(prob: Problem, b, lam: float, iters: int, x0=None, L: float = 1.0,
-          callback=None):
+          callback=None, gradient: str = "adjoint"):
     """Plain FISTA from x0 (zero by default); returns the last x_k."""
     x = np.zeros(prob.ncoef) if x0 is None else np.array(x0, dtype=np.float64)
     y = x.copy()
     t = 1.0
     for k in range(1, iters + 1):
         t_new = t_next(t)
-        x, y = fista_step(prob, x, y, b, (t - 1.0) / t_new, lam, L)
+        x, y = fista_step(prob, x, y, b, (t - 1.0) / t_new, lam, L, gradient)
         t = t_new
         if callback is not None:
             callback(k, x)

@@ -171,10 +171,12 @@ def _cfg1(dt_seed=0):
     return rows, cols, h, psf, b
 
 
+@pytest.mark.parametrize("gradient", ["adjoint", "pinv"])
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
-def test_fista_step_from_oracle_state(dt):
-    """One FISTA iteration from an identical state (k = 5)."""
-    print(f"[fista step] 256x256 {dt}", flush=True)
+def test_fista_step_from_oracle_state(dt, gradient):
+    """One FISTA iteration from an identical state (k = 5), with the true
+    adjoint W^* or with W^dagger in its place."""
+    print(f"[fista step] 256x256 {dt} gradient={gradient}", flush=True)
     rows, cols, h, psf, b = _cfg1()
     prob = ofi.Problem(rows, cols, h, "sym", 3, psf)
     rng = rng_for(5, 0)
@@ -185,12 +187,15 @@ def test_fista_step_from_oracle_state(dt):
     for _ in range(k - 1):
         t = ofi.t_next(t)
     beta = (t - 1.0) / ofi.t_next(t)
-    x_ref, y_ref = ofi.fista_step(prob, x_prev, y, b, beta, lam)
+    x_ref, y_ref = ofi.fista_step(prob, x_prev, y, b, beta, lam, gradient=gradient)
+    if gradient == "pinv":  # the two maps differ in the sym mode
+        x_adj, _ = ofi.fista_step(prob, x_prev, y, b, beta, lam)
+        assert rel(x_adj, x_ref) > 100 * TOL[dt]
     r_ref = prob.A(y) - b
     w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
     bs = ops.BlurSpec(rows, cols, taps=psf)
     bt = dev(b, dt)
-    st = ops.FistaState(w, bs, bt, x0=dev(x_prev, dt))
+    st = ops.FistaState(w, bs, bt, x0=dev(x_prev, dt), gradient=gradient)
     st.y.copy_(dev(y, dt))
     st.k, st.t = k, t
     ops.fista_step(st, bt, lam, want_objective=True)
@@ -226,6 +231,42 @@ def test_fista_trajectory_small_config():
             if k in checks:
                 F = ofi.objective(prob, host(st.x), b, lam)
                 assert abs(F - F_ref[k]) <= tol * F_ref[k], (dt, k, F, F_ref[k])
+
+
+def test_fista_pinv_gradient_trajectory_haar():
+    """The paper's comparison setting (three-level Haar, sym, lambda = 2e-5):
+    100 iterations with W^dagger in the place of W^* against the oracle's
+    iterates (FP32), and the zpd mode, where the maps coincide, giving the
+    same bits with either flag."""
+    print("[fista pinv] 256x256 haar J=3 100 iterations", flush=True)
+    rows, cols, _, psf, b = _cfg1()
+    h = ofl.by_taps(2)
+    prob = ofi.Problem(rows, cols, h, "sym", 3, psf)
+    lam = 2e-5
+    x_ref = {}
+    ofi.fista(prob, b, lam, 100, gradient="pinv",
+              callback=lambda k, x: x_ref.__setitem__(k, x.copy()) if k in (10, 100) else None)
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
+    bs = ops.BlurSpec(rows, cols, taps=psf)
+    bt = dev(b, torch.float32)
+    st = ops.FistaState(w, bs, bt, gradient="pinv")
+    for k in range(1, 101):
+        ops.fista_step(st, bt, lam)
+        if k in x_ref:
+            F = ofi.objective(prob, host(st.x), b, lam)
+            F_ref = ofi.objective(prob, x_ref[k], b, lam)
+            assert abs(F - F_ref) <= 1e-4 * F_ref, (k, F, F_ref)
+            # the two maps' iterates differ by 3.6e-3 (k = 10) and 4.7e-3 (k = 100)
+            assert rel(host(st.x), x_ref[k]) <= 5e-4, k
+    wz = ops.WaveletSpec(rows, cols, 3, lo=h, bc="zpd")
+    outs = []
+    for g in ("adjoint", "pinv"):
+        sz = ops.FistaState(wz, bs, bt, gradient=g)
+        for _ in range(5):
+            ops.fista_step(sz, bt, lam)
+        outs.append(sz.x.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
 
 
 def test_fista_step_deterministic():

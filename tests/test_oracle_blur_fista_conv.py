@@ -189,6 +189,49 @@ def test_fista_step_matches_gradient_step():
     np.testing.assert_allclose(x, np.sign(v) * np.maximum(np.abs(v) - 1e-2, 0), atol=1e-14)
 
 
+@pytest.mark.parametrize("mode", ["zpd", "per"])
+def test_pinv_gradient_equals_adjoint_without_extension(mode):
+    """zpd and per involve no fold, so W^dagger = W^* and the two gradient
+    maps agree."""
+    rows, cols = 24, 32
+    h = fl.by_taps(8)
+    prob = fi.Problem(rows, cols, h, mode, 2, bl.gaussian_taps(1.5, 3))
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(prob.ncoef)
+    b = rng.standard_normal((rows, cols))
+    g = fi.grad(prob, x, b)
+    np.testing.assert_allclose(fi.grad(prob, x, b, "pinv"), g, atol=1e-12 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("L,levels", [(2, 3), (8, 2)])
+def test_pinv_gradient_is_left_inverse_of_W(L, levels):
+    """With the symmetric extension W^dagger is a left inverse of W that is not
+    its adjoint: W maps the pinv gradient back onto R^*(A x - b) exactly, while
+    it differs from the true gradient W^* R^*(A x - b)."""
+    rows, cols = 20, 28
+    h = fl.by_taps(L)
+    psf = bl.gaussian_taps(2.0, 4)
+    prob = fi.Problem(rows, cols, h, "sym", levels, psf)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(prob.ncoef)
+    b = rng.standard_normal((rows, cols))
+    gp = fi.grad(prob, x, b, "pinv")
+    img_grad = bl.R_adj(prob.A(x) - b, psf)
+    back = wv.W(gp, h, "sym", levels, rows, cols)
+    np.testing.assert_allclose(back, img_grad, atol=1e-12 * np.abs(img_grad).max())
+    ga = fi.grad(prob, x, b)
+    assert np.linalg.norm(gp - ga) > 1e-3 * np.linalg.norm(ga)
+    # one step with either map
+    xp = rng.standard_normal(prob.ncoef)
+    xa, _ = fi.fista_step(prob, xp, x, b, 0.3, 1e-2)
+    xq, _ = fi.fista_step(prob, xp, x, b, 0.3, 1e-2, gradient="pinv")
+    v = x - gp
+    np.testing.assert_allclose(xq, np.sign(v) * np.maximum(np.abs(v) - 1e-2, 0), atol=1e-14)
+    assert not np.allclose(xa, xq)
+    with pytest.raises(ValueError):
+        fi.grad(prob, x, b, "transpose")
+
+
 # --------------------------------------------------------------- conv pair
 def paper_S(s, K):
     """The matrix S of x_est = S h (Sec. 'Example 2'): column j holds s shifted
