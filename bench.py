@@ -269,7 +269,8 @@ def bench_adjoint_study() -> dict:
     for taps, name in ((2, "haar_J3_sym"), (8, "db4_J3_sym")):
         r = adjoint_study.run(256, 256, taps, 3, "sym", 2.0, 4, 2e-5, 2500, every=500)
         out[name] = {"blurred": {k: round(v, 6) for k, v in r["blurred"].items()},
-                     **{g: {k: round(r[g][k], 6) for k in ("rel_err", "nonzero_pct", "ssim")}
+                     **{g: {k: round(r[g][k], 6)
+                            for k in ("rel_err", "nonzero_pct", "ssim", "objective")}
                         for g in ("adjoint", "pinv")}}
     return out
 
@@ -377,6 +378,8 @@ def main():
                                                       P(ws), wsn, sp),
             "A*": lambda: lib.aw_apply_A_adjoint(w.c, bsp.c, 0, 1, P(y), P(out_coef), P(ws), wsn,
                                                  sp),
+            "A*_fused": lambda: lib.aw_apply_A_adjoint_fused(w.c, bsp.c, 0, 1, P(y), P(out_coef),
+                                                             P(ws), wsn, sp),
             "W*_level1": lambda: lib.wavelet_synth_adjoint(w1.c, 0, 1, P(y), P(out_coef), P(ws),
                                                            wsn, sp),
             "W_level1": lambda: lib.wavelet_synth(w1.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),

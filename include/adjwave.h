@@ -178,6 +178,19 @@ aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dty
                              int32_t batch, const void* img, void* coef, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* coef = A^* img = W^* R^* img with the blur adjoint and the finest analysis
+ * level in one tile pass: each tile computes R^* img over the image samples its
+ * window reads and analyses them from LDS, so R^* img never reaches memory
+ * (coarser levels run as in aw_apply_A_adjoint). Bitwise equal to
+ * aw_apply_A_adjoint. Float32 only; boundaries zpd or sym (images of at least
+ * L - 1 samples per axis for sym); filter length 2, 8 or 16. Other requests
+ * return AW_EUNSUPPORTED. Same workspace as aw_apply_A_adjoint, which is the
+ * faster of the two on gfx950 (this entry point trades the intermediate
+ * image for recomputed blur halos and a larger LDS footprint). */
+aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype,
+                                   int32_t batch, const void* img, void* coef, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ FISTA */
 
 /* State of FISTA (Beck & Teboulle) on eq. (1) for `batch` independent images

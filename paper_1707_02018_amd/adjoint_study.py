@@ -18,6 +18,7 @@ checkpoints (evaluation only, outside the iteration):
   ssim      mean SSIM of W x_k against the image (Wang et al. 2004: Gaussian
             window sigma 1.5 truncated to 11 taps, K1 = 0.01, K2 = 0.03,
             dynamic range 1, reflected borders)
+  objective F(x_k) of eq. (1); only the true adjoint's iteration minimises it
 """
 from __future__ import annotations
 
@@ -64,12 +65,13 @@ def make_problem(rows: int, cols: int, sigma: float, radius: int, seed: int, dev
     return img, b, bsp
 
 
-def measures(w: ops.WaveletSpec, x, img: np.ndarray) -> dict:
+def measures(w: ops.WaveletSpec, bsp: ops.BlurSpec, b, x, lam: float, img: np.ndarray) -> dict:
     rec = ops.wavelet_synth(w, x).double().cpu().numpy()
     xh = x.cpu().numpy()
+    F = ops.objective(w, bsp, b, x, lam)[0, 2].item()
     return {"rel_err": float(np.linalg.norm(rec - img) / np.linalg.norm(img)),
             "nonzero_pct": float(100.0 * np.count_nonzero(xh) / xh.size),
-            "ssim": ssim(rec, img)}
+            "ssim": ssim(rec, img), "objective": F}
 
 
 def run(rows: int = 256, cols: int = 256, taps: int = 2, levels: int = 3, bc: str = "sym",
@@ -94,8 +96,9 @@ def run(rows: int = 256, cols: int = 256, taps: int = 2, levels: int = 3, bc: st
             ops.fista_step(st, b, lam)
             if k % every == 0 or k == iters:
                 torch.cuda.synchronize()
-                curve.append({"k": k, **measures(w, st.x, img)})
-        out[grad] = {**{key: curve[-1][key] for key in ("rel_err", "nonzero_pct", "ssim")},
+                curve.append({"k": k, **measures(w, bsp, b, st.x, lam, img)})
+        out[grad] = {**{key: curve[-1][key]
+                        for key in ("rel_err", "nonzero_pct", "ssim", "objective")},
                      "curve": curve}
     return out
 

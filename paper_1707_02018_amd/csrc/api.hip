@@ -272,10 +272,27 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
   return AW_OK;
 }
 
-aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* img, void* coef,
-                       void* ws, const WsLayout& l, int pinv, hipStream_t s) {
+aw::AnaLevel ana_desc(const WavePlan& p, aw_dtype dt, const void* img, void* coef, void* ws,
+                      const WsLayout& l, int pinv, int j) {
   const size_t ts = dsize(dt);
-  for (int j = 1; j <= p.J; ++j) {
+  aw::AnaLevel d{};
+  d.in = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
+  d.stride_in = (long long)p.sr[j - 1] * p.sc[j - 1];
+  d.a = (j == p.J) ? coef : wsp(ws, l.a_off[j]);
+  d.stride_a = (j == p.J) ? p.ncoef : (long long)p.sr[j] * p.sc[j];
+  d.hvd = static_cast<char*>(coef) + p.off_hvd[j] * ts;
+  d.stride_hvd = p.ncoef;
+  d.r = {p.sr[j - 1], p.sr[j], p.e};
+  d.c = {p.sc[j - 1], p.sc[j], p.e};
+  d.bc = p.bc;
+  d.pinv = pinv;
+  return d;
+}
+
+aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* img, void* coef,
+                       void* ws, const WsLayout& l, int pinv, hipStream_t s, int j_from = 1) {
+  const size_t ts = dsize(dt);
+  for (int j = j_from; j <= p.J; ++j) {
     aw::AnaLevel d{};
     d.in = (j == 1) ? img : wsp(ws, l.a_off[j - 1]);
     d.stride_in = (long long)p.sr[j - 1] * p.sc[j - 1];
@@ -595,6 +612,27 @@ aw_status aw_apply_A_adjoint(const aw_wavelet* w, const aw_blur* b, aw_dtype dty
                  "blur_adjoint launch");
   if (st != AW_OK) return st;
   st = run_analysis(p, dtype, batch, tmp, coef, workspace, l, 1, s);
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype,
+                                   int32_t batch, const void* img, void* coef, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = op_common(w, b, dtype, batch, img, coef, workspace, workspace_bytes, p, d, l);
+  if (st != AW_OK) return st;
+  if (dtype != AW_F32) return fail(AW_EUNSUPPORTED, "fused A^* runs in float32 only");
+  const aw::AnaLevel d1 = ana_desc(p, dtype, img, coef, workspace, l, 1, 1);
+  if (!aw::blur_ana_supported(p.L, d1, d))
+    return fail(AW_EUNSUPPORTED,
+                "fused A^* needs zpd or sym, filter length 2, 8 or 16 and, for sym, images of "
+                "at least L - 1 samples per axis");
+  hipStream_t s = (hipStream_t)stream;
+  st = hip_check(aw::launch_blur_ana(p.L, p.lo, d1, d, batch, s), "fused blur-analysis launch");
+  if (st != AW_OK) return st;
+  st = run_analysis(p, dtype, batch, img, coef, workspace, l, 1, s, 2);
   return st == AW_OK ? ok() : st;
 }
 

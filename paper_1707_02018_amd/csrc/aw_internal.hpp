@@ -33,6 +33,30 @@ __host__ __device__ inline int posmod(int a, int b) {
   return r < 0 ? r + b : r;
 }
 
+// Sums of NV values over an NT-thread workgroup in a fixed order: a butterfly
+// within each wave64, then the NT / 64 wave sums in wave order (LDS red:
+// NV x NT / 64 doubles). The totals are left in thread 0's v; every thread of
+// the workgroup must call it (one barrier).
+template <int NT, int NV>
+__device__ inline void block_sums(double (&v)[NV], double* red) {
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v[q] += __shfl_xor(v[q], m, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q * NW + (threadIdx.x >> 6)] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[q * NW + w];
+      v[q] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Extension index maps.
 
@@ -50,6 +74,20 @@ __host__ __device__ inline int src_index(int i, int N, int bc) {
     return posmod(i, N);
   }
   return i;
+}
+
+// Half-point reflexive extension of the blur (any distance): the source of
+// position m, and whether m is reached through an odd number of reflections
+// (orientation reversed).
+__host__ __device__ inline int refl_idx(int m, int N) {
+  if (m >= -N && m < 2 * N) return m < 0 ? -1 - m : (m >= N ? 2 * N - 1 - m : m);
+  const int j = posmod(m, 2 * N);
+  return j < N ? j : 2 * N - 1 - j;
+}
+
+__host__ __device__ inline bool refl_odd(int m, int N) {
+  if (m >= -N && m < 2 * N) return m < 0 || m >= N;
+  return (floordiv(m, N) & 1) != 0;
 }
 
 // Calls f(n) for every extended position n = i + e, i in [-e, N+e), whose
@@ -283,6 +321,11 @@ int fista_prox_blocks(long long n);
 bool synth_blur_supported(int L, const SynthLevel& d, const BlurDesc& b);
 hipError_t launch_synth_blur(int L, const double* lo, const SynthLevel& d, const BlurDesc& b,
                              const void* sub, void* y, int batch, hipStream_t s);
+// A^* = W^* R^* with R^* fused into the finest analysis level (FP32; zpd or
+// sym; filter lengths 2, 8, 16); d.in is the image R^* applies to.
+bool blur_ana_supported(int L, const AnaLevel& d, const BlurDesc& b);
+hipError_t launch_blur_ana(int L, const double* lo, const AnaLevel& d, const BlurDesc& b,
+                           int batch, hipStream_t s);
 size_t synth_chain_plan(int dtype, int L, SynthChain& c);
 hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size_t lds, int batch,
                               hipStream_t s);

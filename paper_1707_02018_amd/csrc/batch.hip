@@ -38,25 +38,18 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(
     int n, const int* __restrict__ tile_prefix, const double* __restrict__ r_part,
     const int* __restrict__ blk_prefix, const double* __restrict__ l1_part,
     const double* __restrict__ dx_part, const int* __restrict__ active, double* __restrict__ obj) {
-  __shared__ double red[3][256];
+  __shared__ double red[3 * 256 / 64];
   const int i = blockIdx.x;
   if (i >= n || (active && !active[i])) return;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int t = tile_prefix[i] + threadIdx.x; t < tile_prefix[i + 1]; t += 256) a += r_part[t];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int t = tile_prefix[i] + threadIdx.x; t < tile_prefix[i + 1]; t += 256) v[0] += r_part[t];
   for (int t = blk_prefix[i] + threadIdx.x; t < blk_prefix[i + 1]; t += 256) {
-    b += l1_part[t];
-    c += dx_part[t];
+    v[1] += l1_part[t];
+    v[2] += dx_part[t];
   }
-  red[0][threadIdx.x] = a;
-  red[1][threadIdx.x] = b;
-  red[2][threadIdx.x] = c;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) obj[3 * i + threadIdx.x] = red[threadIdx.x][0];
+  block_sums<256, 3>(v, red);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) obj[3 * i + q] = v[q];
 }
 
 __global__ void batch_counter_kernel(int* counter) {

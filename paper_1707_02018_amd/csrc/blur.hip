@@ -39,19 +39,6 @@ struct BlurCfg<double, VAR> {
   using V = double2;
 };
 
-__device__ inline int refl_idx(int m, int N) {
-  if (m >= -N && m < 2 * N) return m < 0 ? -1 - m : (m >= N ? 2 * N - 1 - m : m);
-  const int j = posmod(m, 2 * N);
-  return j < N ? j : 2 * N - 1 - j;
-}
-
-// position m of the reflexive extension reached through an odd number of
-// reflections (orientation reversed)
-__device__ inline bool refl_odd(int m, int N) {
-  if (m >= -N && m < 2 * N) return m < 0 || m >= N;
-  return (floordiv(m, N) & 1) != 0;
-}
-
 template <typename T, int R, bool ADJ, int VAR>
 __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restrict__ X,
                                           T* __restrict__ Y, const T* __restrict__ SUB,
@@ -67,7 +54,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
   __shared__ __align__(16) T sx[WR * SXS];
   __shared__ __align__(16) T sh[WR * TC];
   __shared__ int rtab[WR], ctab[WC];
-  __shared__ double red[NT];
+  __shared__ double red[NT / 64];
 
   const int N = a.rows, M = a.cols;
   const int r0 = by * TR, c0 = bx * TC;
@@ -215,13 +202,9 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
     }
   }
   if (part_out) {
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) *part_out = red[0];
+    double v[1] = {part};
+    block_sums<NT, 1>(v, red);
+    if (threadIdx.x == 0) *part_out = v[0];
   }
 }
 

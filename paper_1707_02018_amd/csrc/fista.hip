@@ -20,7 +20,7 @@ int fista_prox_blocks(long long n) {
 template <typename T>
 __global__ __launch_bounds__(kProxThreads) void l1_partials_kernel(long long n, const T* __restrict__ x,
                                                                    double* __restrict__ partials) {
-  __shared__ double red[kProxThreads];
+  __shared__ double red[kProxThreads / 64];
   const T* X = x + (long long)blockIdx.y * n;
   double l1 = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -28,13 +28,9 @@ __global__ __launch_bounds__(kProxThreads) void l1_partials_kernel(long long n, 
     const T v = X[i];
     l1 += (double)(v < T(0) ? -v : v);
   }
-  red[threadIdx.x] = l1;
-  __syncthreads();
-  for (int s = kProxThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  double v[1] = {l1};
+  block_sums<kProxThreads, 1>(v, red);
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
 }
 
 hipError_t launch_l1_partials(int dtype, int batch, long long n, const void* x, double* partials,
@@ -63,17 +59,12 @@ hipError_t launch_objective_finalize(int batch, double lambda, double* obj, hipS
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int nparts, const double* __restrict__ p,
                                                               double scale, double* __restrict__ out,
                                                               int out_stride, int out_off) {
-  __shared__ double red[256];
+  __shared__ double red[256 / 64];
   const double* P = p + (long long)blockIdx.x * nparts;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) acc += P[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + out_off] = scale * red[0];
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nparts; i += 256) v[0] += P[i];
+  block_sums<256, 1>(v, red);
+  if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + out_off] = scale * v[0];
 }
 
 hipError_t launch_reduce_partials(int batch, int nparts, const double* partials, double scale,

@@ -14,9 +14,17 @@
 //
 // The synthesised values and the blur arithmetic are those of the separate
 // kernels, so the result is bitwise identical to synthesis followed by blur.
+//
+// A^* = W^* R^* with the blur adjoint fused into the finest analysis level
+// (opt-in entry aw_apply_A_adjoint_fused): each half-height analysis tile
+// computes R^* r over the image samples its window reads and analyses them
+// from LDS (ana_tile with a blur radius), so R^* r never reaches memory; the
+// coarser levels run as in aw_apply_A_adjoint. Bitwise equal to the
+// two-kernel A^*.
 #include <algorithm>
 #include <type_traits>
 
+#include "ana_tile.hpp"
 #include "aw_internal.hpp"
 #include "synth_tile.hpp"
 
@@ -230,7 +238,70 @@ hipError_t fused_dispatch(int L, const SynthLevel& d, const double* lo, const Bl
   }
 }
 
+// ------------------------------------------- R^* fused into analysis level 1
+constexpr int kBlurAnaVar = 1;  // half-height tiles: the blur window fits static LDS
+
+template <int L, int BC, int R>
+__global__ __launch_bounds__(512) void blur_ana_kernel(AnaLevel d, Taps<float> f,
+                                                       BlurArgs<float> a) {
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  ana_tile<float, L, BC, kBlurAnaVar, false, R>(d, f, tx, ty, tz, ProxEpi{}, &a);
+}
+
+template <int L, int BC, int R>
+hipError_t launch_blur_ana_t(const double* lo, const AnaLevel& d, const BlurDesc& b, int batch,
+                             hipStream_t s) {
+  using Tile = AnaTile<float, kBlurAnaVar>;
+  dim3 grid((d.c.K + Tile::TKC - 1) / Tile::TKC, (d.r.K + Tile::TKR - 1) / Tile::TKR, batch);
+  hipLaunchKernelGGL((blur_ana_kernel<L, BC, R>), grid, dim3(Tile::NT), 0, s, d,
+                     make_taps<float>(lo, L), make_blur_args<float, true>(b));
+  return hipGetLastError();
+}
+
+template <int L, int BC>
+hipError_t blur_ana_R(const double* lo, const AnaLevel& d, const BlurDesc& b, int batch,
+                      hipStream_t s) {
+  switch (b.radius) {
+#define AW_BLUR_ANA_R(r) \
+  case r: return launch_blur_ana_t<L, BC, r>(lo, d, b, batch, s);
+    AW_BLUR_ANA_R(0) AW_BLUR_ANA_R(1) AW_BLUR_ANA_R(2) AW_BLUR_ANA_R(3) AW_BLUR_ANA_R(4)
+    AW_BLUR_ANA_R(5) AW_BLUR_ANA_R(6) AW_BLUR_ANA_R(7) AW_BLUR_ANA_R(8) AW_BLUR_ANA_R(9)
+    AW_BLUR_ANA_R(10) AW_BLUR_ANA_R(11) AW_BLUR_ANA_R(12)
+#undef AW_BLUR_ANA_R
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int L>
+hipError_t blur_ana_BC(const double* lo, const AnaLevel& d, const BlurDesc& b, int batch,
+                       hipStream_t s) {
+  switch (d.bc) {
+    case ZPD: return blur_ana_R<L, ZPD>(lo, d, b, batch, s);
+    case SYM: return blur_ana_R<L, SYM>(lo, d, b, batch, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+bool blur_ana_supported(int L, const AnaLevel& d, const BlurDesc& b) {
+  if (d.bc != ZPD && d.bc != SYM) return false;
+  if (d.bc == SYM && (d.r.N < d.r.e || d.c.N < d.c.e)) return false;  // two-step fold
+  if (L != 2 && L != 8 && L != 16) return false;
+  if (b.radius < 0 || b.radius > kMaxRadius) return false;
+  return d.r.N == b.rows && d.c.N == b.cols;
+}
+
+hipError_t launch_blur_ana(int L, const double* lo, const AnaLevel& d, const BlurDesc& b,
+                           int batch, hipStream_t s) {
+  switch (L) {
+    case 2: return blur_ana_BC<2>(lo, d, b, batch, s);
+    case 8: return blur_ana_BC<8>(lo, d, b, batch, s);
+    case 16: return blur_ana_BC<16>(lo, d, b, batch, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 bool synth_blur_supported(int L, const SynthLevel& d, const BlurDesc& b) {
   if (d.bc != ZPD && d.bc != SYM && d.bc != PER) return false;

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "ana_tile.hpp"
 #include "aw_internal.hpp"
 #include "synth_tile.hpp"
 
@@ -249,280 +250,6 @@ hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size
 }
 
 // ----------------------------------------------------------------- analysis
-template <typename T, int L, int BC, int VAR, bool PROX = false>
-__device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, int bx, int by,
-                                         int img, const ProxEpi& pe = ProxEpi{}) {
-  constexpr int TKR = AnaTile<T, VAR>::TKR, TKC = AnaTile<T, VAR>::TKC, NT = AnaTile<T, VAR>::NT;
-  // output ownership of step 3: thread = column kk, KB consecutive rows
-  constexpr int RBLK = NT / TKC;
-  constexpr int KB = TKR / RBLK;
-  const int kk = threadIdx.x % TKC;
-  const int rb = threadIdx.x / TKC;
-  // fused update: y_k and x_{k-1} of the owned coefficients are fetched
-  // first, so their latency overlaps the staging below
-  T py[KB][4], px[KB][4];
-  if constexpr (PROX) {
-    const long long band = (long long)d.r.K * d.c.K;
-    const int kc = bx * TKC + kk;
-#pragma unroll
-    for (int r = 0; r < KB; ++r) {
-      const int kr = by * TKR + rb * KB + r;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) py[r][q] = px[r][q] = T(0);
-      if (kr < d.r.K && kc < d.c.K) {
-        const long long off = (long long)kr * d.c.K + kc;
-        const T* Y = static_cast<const T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
-        const T* X = static_cast<const T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-          py[r][q] = Y[(q - 1) * band];
-          px[r][q] = X[(q - 1) * band];
-        }
-        if (pe.x_a) {
-          py[r][0] = static_cast<const T*>(pe.y_a)[(long long)img * d.stride_a + off];
-          px[r][0] = static_cast<const T*>(pe.x_a)[(long long)img * d.stride_a + off];
-        }
-      }
-    }
-  }
-  constexpr int NWR = 2 * TKR + L - 2, NWC = 2 * TKC + L - 2;
-  constexpr int VW = 16 / sizeof(T);                       // elements per 16-byte LDS read
-  constexpr int SUS = ((NWC + VW - 1) / VW) * VW + VW;     // input row stride
-  constexpr int NV = (2 * VW + L - 2 + VW - 1) / VW;       // vectors per pass-1 item
-  using V2 = typename Vec<T>::V2;
-  using V4 = typename Vec<T>::V4;
-  __shared__ __align__(16) T su[NWR * SUS];
-  __shared__ __align__(16) V2 slh[NWR * TKC];
-
-  const int Nr = d.r.N, Nc = d.c.N, Kr = d.r.K, Kc = d.c.K;
-  const int er = d.r.e, ec = d.c.e;
-  const int kr0 = by * TKR, kr1 = min(kr0 + TKR, Kr);
-  const int kc0 = bx * TKC, kc1 = min(kc0 + TKC, Kc);
-  const int nlo_r = (BC == PER) ? 2 * kr0 : 2 * kr0 - L + 2;
-  const int nlo_c = (BC == PER) ? 2 * kc0 : 2 * kc0 - L + 2;
-  const int Mr = Nr + 2 * er, Mc = Nc + 2 * ec;
-  const T* Y = static_cast<const T*>(d.in) + (long long)img * d.stride_in;
-  const bool interior = (BC == PER) ? (nlo_r + NWR <= Nr && nlo_c + NWC <= Nc)
-                                    : (nlo_r >= 2 * er && nlo_r + NWR <= Nr && nlo_c >= 2 * ec &&
-                                       nlo_c + NWC <= Nc);
-
-  // 1. gather u(n) = w(src) y[src(n - e)] (zero outside [0, M)); all loads
-  //    of a thread are issued before its LDS writes
-  if (interior && (Nc % VW) == 0) {
-    const int g0 = nlo_c - ec;                  // first input column of the window
-    const int a0 = (g0 >= 0 ? g0 / VW : -((-g0 + VW - 1) / VW)) * VW;
-    const int off = g0 - a0;                    // 0 .. VW-1
-    constexpr int NVR = (NWC + 2 * VW - 2) / VW + 1;  // vectors per row (upper bound)
-    constexpr int NVEC = NWR * NVR;
-    constexpr int IT = (NVEC + NT - 1) / NT;
-    using LV = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-    LV buf[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NVEC) {
-        const int i = idx / NVR, jv = idx - (idx / NVR) * NVR;
-        const int gc = a0 + jv * VW;
-        if (gc + VW <= Nc)
-          buf[it] = *reinterpret_cast<const LV*>(Y + (long long)(nlo_r + i - er) * Nc + gc);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NVEC) {
-        const int i = idx / NVR, jv = idx - (idx / NVR) * NVR;
-        const int gc = a0 + jv * VW;
-        if (gc + VW <= Nc) {
-          T e[VW];
-          if constexpr (VW == 4) {
-            e[0] = buf[it].x; e[1] = buf[it].y; e[2] = buf[it].z; e[3] = buf[it].w;
-          } else {
-            e[0] = buf[it].x; e[1] = buf[it].y;
-          }
-#pragma unroll
-          for (int u = 0; u < VW; ++u) {
-            const int j = jv * VW + u - off;
-            if (j >= 0 && j < NWC) su[i * SUS + j] = e[u];
-          }
-        }
-      }
-    }
-  } else {
-    // per-row / per-column source index and weight (1/mult for W^*, 1 for
-    // W^dagger, 0 outside the extended signal), then one gather loop
-    __shared__ int rsrc[NWR], csrc[NWC];
-    __shared__ T rwt[NWR], cwt[NWC];
-    for (int i = threadIdx.x; i < NWR + NWC; i += blockDim.x) {
-      const bool isr = i < NWR;
-      const int n = isr ? nlo_r + i : nlo_c + (i - NWR);
-      const int Nn = isr ? Nr : Nc, ee = isr ? er : ec, Mm = Nn + 2 * ee;
-      int src = 0;
-      T wgt = T(0);
-      if (BC == PER) {
-        src = posmod(n, Nn);
-        wgt = T(1);
-      } else if (n >= 0 && n < Mm) {
-        src = src_index(n - ee, Nn, BC);
-        wgt = d.pinv ? T(1) / T(multiplicity(src, Nn, ee, BC)) : T(1);
-      }
-      if (isr) {
-        rsrc[i] = src;
-        rwt[i] = wgt;
-      } else {
-        csrc[i - NWR] = src;
-        cwt[i - NWR] = wgt;
-      }
-    }
-    __syncthreads();
-    constexpr int IT2 = (NWR * NWC + NT - 1) / NT;  // every load issued before any LDS write
-    T v[IT2];
-#pragma unroll
-    for (int it = 0; it < IT2; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NWR * NWC) {
-        const int i = idx / NWC, j = idx - (idx / NWC) * NWC;
-        v[it] = Y[(long long)rsrc[i] * Nc + csrc[j]] * (rwt[i] * cwt[j]);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT2; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NWR * NWC) {
-        const int i = idx / NWC, j = idx - (idx / NWC) * NWC;
-        su[i * SUS + j] = v[it];
-      }
-    }
-  }
-  for (int idx = threadIdx.x; idx < NWR * (SUS - NWC); idx += blockDim.x) {
-    const int i = idx / (SUS - NWC), j = idx - (idx / (SUS - NWC)) * (SUS - NWC);
-    su[i * SUS + NWC + j] = T(0);
-  }
-  __syncthreads();
-
-  // 2. filter along columns, two output columns per item:
-  //    (lo, hi)[i][kc] = sum_j (h, g)[j] u(i, 2 kc + j)
-  constexpr int CP = TKC / 2;
-  for (int item = threadIdx.x; item < NWR * CP; item += blockDim.x) {
-    const int i = item / CP, cp = item - (item / CP) * CP;
-    const T* row = su + i * SUS + 4 * cp;
-    T w[NV * VW];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if constexpr (VW == 4) {
-        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
-        w[4 * v] = q.x; w[4 * v + 1] = q.y; w[4 * v + 2] = q.z; w[4 * v + 3] = q.w;
-      } else {
-        const double2 q = *reinterpret_cast<const double2*>(row + 2 * v);
-        w[2 * v] = q.x; w[2 * v + 1] = q.y;
-      }
-    }
-    T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      lo0 += f.h[j] * w[j];
-      hi0 += f.g[j] * w[j];
-      lo1 += f.h[j] * w[j + 2];
-      hi1 += f.g[j] * w[j + 2];
-    }
-    V4 o;
-    o.x = lo0; o.y = hi0; o.z = lo1; o.w = hi1;
-    *reinterpret_cast<V4*>(slh + i * TKC + 2 * cp) = o;
-  }
-  __syncthreads();
-
-  // 3. filter along rows: thread = column kc and KB consecutive coefficient rows
-  constexpr int NW = 2 * KB + L - 2;
-  V2 win[NW];
-#pragma unroll
-  for (int i = 0; i < NW; ++i) win[i] = slh[(2 * rb * KB + i) * TKC + kk];
-  T* Aout = static_cast<T*>(d.a) + (long long)img * d.stride_a;
-  T* HVD = static_cast<T*>(d.hvd) + (long long)img * d.stride_hvd;
-  const long long band = (long long)Kr * Kc;
-  const int kc = kc0 + kk;
-  double l1 = 0.0, dx = 0.0;
-  T beta = T(0);
-  if constexpr (PROX) {
-    if (pe.beta_tab) {
-      int k = *pe.counter;
-      k = k < 1 ? 1 : (k > pe.beta_len ? pe.beta_len : k);
-      beta = (T)pe.beta_tab[k - 1];
-    } else {
-      beta = (T)pe.beta;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < KB; ++r) {
-    T a = T(0), H = T(0), V = T(0), D = T(0);
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const V2 q = win[2 * r + j];
-      a += f.h[j] * q.x;
-      H += f.g[j] * q.x;
-      V += f.h[j] * q.y;
-      D += f.g[j] * q.y;
-    }
-    const int kr = kr0 + rb * KB + r;
-    if (kr < kr1 && kc < kc1) {
-      const long long off = (long long)kr * Kc + kc;
-      if constexpr (PROX) {
-        const T g[4] = {a, H, V, D};
-        T xn[4];
-        const T il = (T)pe.inv_L, th = (T)pe.thresh, be = beta;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T v = py[r][q] - g[q] * il;
-          xn[q] = v > th ? v - th : (v < -th ? v + th : T(0));
-        }
-        T* Xh = static_cast<T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
-        T* Yh = static_cast<T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-          Yh[(q - 1) * band] = xn[q] + be * (xn[q] - px[r][q]);
-          Xh[(q - 1) * band] = xn[q];
-          l1 += (double)(xn[q] < T(0) ? -xn[q] : xn[q]);
-          dx += (double)(xn[q] - px[r][q]) * (double)(xn[q] - px[r][q]);
-        }
-        if (pe.x_a) {
-          const long long oa = (long long)img * d.stride_a + off;
-          static_cast<T*>(pe.y_a)[oa] = xn[0] + be * (xn[0] - px[r][0]);
-          static_cast<T*>(pe.x_a)[oa] = xn[0];
-          l1 += (double)(xn[0] < T(0) ? -xn[0] : xn[0]);
-          dx += (double)(xn[0] - px[r][0]) * (double)(xn[0] - px[r][0]);
-        } else {
-          Aout[off] = a;
-        }
-      } else {
-        Aout[off] = a;
-        HVD[off] = H;
-        HVD[band + off] = V;
-        HVD[2 * band + off] = D;
-      }
-    }
-  }
-  if constexpr (PROX) {
-    if (pe.partials) {  // fixed-order tile sums of |x_k| (and (x_k - x_{k-1})^2)
-      __shared__ double red[2][NT];
-      red[0][threadIdx.x] = l1;
-      red[1][threadIdx.x] = dx;
-      __syncthreads();
-      for (int w = NT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-          red[0][threadIdx.x] += red[0][threadIdx.x + w];
-          red[1][threadIdx.x] += red[1][threadIdx.x + w];
-        }
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) {
-        const int gx = (Kc + TKC - 1) / TKC;
-        const long long slot = (long long)img * pe.pstride + pe.pbase + by * gx + bx;
-        pe.partials[slot] = red[0][0];
-        if (pe.dx_partials) pe.dx_partials[slot] = red[1][0];
-      }
-    }
-  }
-}
-
 template <typename T, int L, int BC, int VAR>
 __global__ __launch_bounds__(512) void ana_level_kernel(AnaLevel d, Taps<T> f) {
   int tx, ty, tz;

@@ -262,6 +262,21 @@ def apply_A_adjoint(w: WaveletSpec, b: BlurSpec, img: torch.Tensor, out=None) ->
     return out
 
 
+def apply_A_adjoint_fused(w: WaveletSpec, b: BlurSpec, img: torch.Tensor,
+                          out=None) -> torch.Tensor:
+    """A^* img with the blur adjoint fused into the finest analysis level
+    (float32; zpd or sym; 2, 8 or 16 taps)."""
+    _dev(img)
+    batch = _batch_img(img, w.rows, w.cols)
+    if out is None:
+        out = torch.empty(img.shape[:-2] + (w.ncoef,), dtype=img.dtype, device=img.device)
+    ws, n = _workspace(w, b, img, batch)
+    check("aw_apply_A_adjoint_fused",
+          load().aw_apply_A_adjoint_fused(w.c, b.c, _dtype_code(img), batch, _ptr(img),
+                                          _ptr(_dev(out)), _ptr(ws), n, _stream(img)))
+    return out
+
+
 # ------------------------------------------------------------------ FISTA
 class FistaState:
     """Device buffers and counters of one FISTA run (x, y coefficient

@@ -43,3 +43,5 @@ def test_study_measures_match_oracle(taps):
         assert abs(got["rel_err"] - rel) <= 1e-3 * rel, (grad, got["rel_err"], rel)
         assert abs(got["nonzero_pct"] - nz) <= 0.5, (grad, got["nonzero_pct"], nz)
         assert abs(got["ssim"] - adjoint_study.ssim(rec, img)) <= 1e-4
+        F = ofi.objective(prob, x, bh, lam)
+        assert abs(got["objective"] - F) <= 1e-4 * F, (grad, got["objective"], F)
