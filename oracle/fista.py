@@ -33,10 +33,11 @@ class Problem:
 
     def __init__(self, rows, cols, h, mode, levels, taps):
         self.rows, self.cols = rows, cols
-        self.h = np.asarray(h, dtype=np.float64)
+        self.h = (tuple(np.asarray(f, dtype=np.float64) for f in h) if isinstance(h, tuple)
+                  else np.asarray(h, dtype=np.float64))
         self.mode, self.levels = mode, levels
         self.taps = np.asarray(taps, dtype=np.float64)
-        self.ncoef = wv.layout(rows, cols, len(h), mode, levels)[0]
+        self.ncoef = wv.layout(rows, cols, wv.flen(h), mode, levels)[0]
 
     def A(self, x):
         return bl.R(wv.W(x, self.h, self.mode, self.levels, self.rows, self.cols), self.taps)

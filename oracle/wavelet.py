@@ -19,6 +19,12 @@ One level with extension E (oracle.extension):
     W^*      = Phi (E^dagger)^*      (eq. 2: the true adjoint)
     (W^dagger)^* = E^* Phi^*         (synthesis with a summing fold)
 
+Biorthogonal filters (Sec. "The adjoint for biorthogonal wavelets") are passed
+as a pair h = (h_syn, h_ana): W and its adjoint W^* use the synthesis side,
+W^dagger and (W^dagger)^* the analysis side, so that W^* = W~^dagger_zpd
+(E^dagger)^* (eq. 4) is the analysis with the dual (synthesis) filters under
+the same (E^dagger)^* fold; W^*_zpd no longer equals W^dagger_zpd.
+
 Mode 'per' is the critically sampled circular transform,
 c_f[k] = sum_q f[q] y[(2k+q) mod N], K = N/2, which is square and orthogonal,
 so W^* = W^dagger = W^{-1}.
@@ -35,7 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import extension as ext
-from .filters import highpass
+from .filters import flen, side_taps
 
 MODES = ("zpd", "sym", "per", "per_ext")
 
@@ -113,10 +119,12 @@ def per_syn(c: np.ndarray, f: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------- 1-D one level, any axis
-def ana1(y: np.ndarray, h: np.ndarray, mode: str, axis: int, weights: str):
+def ana1(y: np.ndarray, h, mode: str, axis: int, weights: str):
     """One analysis level along ``axis``. weights='ones' -> W^dagger = Phi E;
-    weights='pinv' -> W^* = Phi (E^dagger)^*. Returns (lo, hi)."""
-    g = highpass(h)
+    weights='pinv' -> W^* = Phi (E^dagger)^*. Returns (lo, hi). For a
+    biorthogonal pair W^dagger filters with the analysis side and W^*, the
+    adjoint of the synthesis, with the synthesis side (eq. 4)."""
+    h, g = side_taps(h, "syn" if weights == "pinv" else "ana")
     y = np.moveaxis(y, axis, -1)
     if mode == "per":
         lo, hi = per_ana(y, h), per_ana(y, g)
@@ -127,11 +135,11 @@ def ana1(y: np.ndarray, h: np.ndarray, mode: str, axis: int, weights: str):
     return np.moveaxis(lo, -1, axis), np.moveaxis(hi, -1, axis)
 
 
-def syn1(lo: np.ndarray, hi: np.ndarray, h: np.ndarray, mode: str, N: int, axis: int,
-         weights: str):
-    """One synthesis level along ``axis``. weights='pinv' -> W = E^dagger Phi^*;
-    weights='ones' -> (W^dagger)^* = E^* Phi^*."""
-    g = highpass(h)
+def syn1(lo: np.ndarray, hi: np.ndarray, h, mode: str, N: int, axis: int, weights: str):
+    """One synthesis level along ``axis``. weights='pinv' -> W = E^dagger Phi^*
+    (synthesis side of a biorthogonal pair); weights='ones' ->
+    (W^dagger)^* = E^* Phi^* (analysis side)."""
+    h, g = side_taps(h, "syn" if weights == "pinv" else "ana")
     lo = np.moveaxis(lo, axis, -1)
     hi = np.moveaxis(hi, axis, -1)
     if mode == "per":
@@ -147,7 +155,7 @@ def syn1(lo: np.ndarray, hi: np.ndarray, h: np.ndarray, mode: str, N: int, axis:
 
 
 # ----------------------------------------------------------- 2-D one level
-def ana2(img: np.ndarray, h: np.ndarray, mode: str, weights: str):
+def ana2(img: np.ndarray, h, mode: str, weights: str):
     """(a, H, V, D) of one 2-D level; rows = axis -2, columns = axis -1."""
     lo_c, hi_c = ana1(img, h, mode, axis=-1, weights=weights)
     a, H = ana1(lo_c, h, mode, axis=-2, weights=weights)
@@ -155,7 +163,7 @@ def ana2(img: np.ndarray, h: np.ndarray, mode: str, weights: str):
     return a, H, V, D
 
 
-def syn2(a, H, V, D, h: np.ndarray, mode: str, rows: int, cols: int, weights: str):
+def syn2(a, H, V, D, h, mode: str, rows: int, cols: int, weights: str):
     """Inverse structure of ``ana2`` (synthesis of one 2-D level)."""
     lo_c = syn1(a, H, h, mode, rows, axis=-2, weights=weights)
     hi_c = syn1(V, D, h, mode, rows, axis=-2, weights=weights)
@@ -191,7 +199,7 @@ def _unpack(x: np.ndarray, sr, sc, levels: int):
     return a_J, details
 
 
-def analysis(img: np.ndarray, h: np.ndarray, mode: str, levels: int, weights: str = "ones"):
+def analysis(img: np.ndarray, h, mode: str, levels: int, weights: str = "ones"):
     """J-level 2-D analysis. weights='ones' gives W^dagger, 'pinv' gives W^*."""
     img = np.asarray(img, dtype=np.float64)
     a = img
@@ -202,11 +210,11 @@ def analysis(img: np.ndarray, h: np.ndarray, mode: str, levels: int, weights: st
     return _pack(a, details[::-1])
 
 
-def synthesis(x: np.ndarray, h: np.ndarray, mode: str, levels: int, rows: int, cols: int,
+def synthesis(x: np.ndarray, h, mode: str, levels: int, rows: int, cols: int,
               weights: str = "pinv"):
     """J-level 2-D synthesis. weights='pinv' gives W, 'ones' gives (W^dagger)^*."""
     x = np.asarray(x, dtype=np.float64)
-    _, sr, sc = layout(rows, cols, len(h), mode, levels)
+    _, sr, sc = layout(rows, cols, flen(h), mode, levels)
     a, details = _unpack(x, sr, sc, levels)
     for idx, j in enumerate(range(levels, 0, -1)):
         H, V, D = details[idx]

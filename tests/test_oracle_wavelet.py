@@ -203,3 +203,80 @@ def test_layout_sizes():
     assert wv.layout(32, 32, 8, "sym", 4)[0] == 6831
     with pytest.raises(ValueError):
         wv.level_sizes(12, 8, "per", 3)
+
+
+# ------------------------------------------------ biorthogonal CDF 9/7 (eq. 4)
+def test_cdf97_filters():
+    """Symmetric 7- and 9-tap low-pass filters centred on the same index, each
+    summing to sqrt(2), biorthogonal under even shifts, four vanishing moments
+    on both high-pass filters, and the product filter of the construction
+    (H_a conj H_s = 2 cos^8 P at sampled frequencies)."""
+    hs, ha = fl.cdf97()
+    assert np.count_nonzero(np.abs(hs) > 1e-15) == 7
+    assert np.count_nonzero(np.abs(ha) > 1e-15) == 9
+    np.testing.assert_allclose(hs[1:8], hs[1:8][::-1], atol=1e-15)
+    np.testing.assert_allclose(ha[0:9], ha[0:9][::-1], atol=1e-15)
+    assert abs(hs.sum() - S2) < 1e-14 and abs(ha.sum() - S2) < 1e-14
+    for m in range(-4, 5):  # linear cross-correlation at even lags
+        r = sum(hs[k] * ha[k + 2 * m] for k in range(10) if 0 <= k + 2 * m < 10)
+        assert abs(r - (1.0 if m == 0 else 0.0)) < 1e-14, (m, r)
+    k = np.arange(10)
+    for g in (fl.highpass(ha), fl.highpass(hs)):
+        for p in range(4):
+            assert abs(np.sum(g * k ** p)) < 1e-9 * max(1, 10 ** p), p
+    w = np.linspace(0, np.pi, 17)
+    z = np.exp(-1j * np.outer(w, k - 4))
+    Hs, Ha = z @ hs, z @ ha
+    y = np.sin(w / 2) ** 2
+    P = 1 + 4 * y + 10 * y ** 2 + 20 * y ** 3
+    np.testing.assert_allclose(Ha * np.conj(Hs), 2 * np.cos(w / 2) ** 8 * P, atol=1e-13)
+
+
+def _mats_bior(N, mode):
+    h = fl.cdf97()
+    K = wv.coef_len(N, 10, mode)
+
+    def ana(weights):
+        return wv.dense(lambda y: np.concatenate(wv.ana1(y, h, mode, -1, weights), axis=-1), N)
+
+    def syn(weights):
+        return wv.dense(lambda c: wv.syn1(c[..., :K], c[..., K:], h, mode, N, -1, weights), 2 * K)
+    return ana("ones"), ana("pinv"), syn("pinv"), syn("ones")
+
+
+@pytest.mark.parametrize("mode", ["zpd", "sym", "per_ext", "per"])
+@pytest.mark.parametrize("N", [10, 18, 40])
+def test_cdf97_one_level(mode, N):
+    """One level: W W^dagger = I (perfect reconstruction), W^* = W^T,
+    (W^dagger)^* = (W^dagger)^T, and, unlike the orthogonal case, W^*_zpd !=
+    W^dagger_zpd: the adjoint analyses with the synthesis (dual) filters."""
+    Wd, Ws, Wm, Wda = _mats_bior(N, mode)
+    np.testing.assert_allclose(Wm @ Wd, np.eye(N), atol=1e-12)
+    np.testing.assert_allclose(Ws, Wm.T, atol=1e-14)
+    np.testing.assert_allclose(Wda, Wd.T, atol=1e-14)
+    assert np.abs(Ws - Wd).max() > 1e-2
+    if mode == "zpd":
+        # eq. 4 with E = I: W^*_zpd is the analysis W~^dagger_zpd of the dual
+        # transform, i.e. the primal analysis with the two sides swapped
+        hs, ha = fl.cdf97()
+        K = wv.coef_len(N, 10, mode)
+        dual = wv.dense(lambda y: np.concatenate(wv.ana1(y, (ha, hs), mode, -1, "ones"),
+                                                 axis=-1), N)
+        np.testing.assert_allclose(Ws, dual, atol=1e-14)
+        assert K == (N + 9) // 2
+
+
+@pytest.mark.parametrize("mode,J,R,C", [("sym", 2, 12, 20), ("zpd", 2, 10, 14),
+                                        ("per", 2, 8, 16), ("per_ext", 1, 12, 10),
+                                        ("sym", 3, 10, 6)])
+def test_cdf97_multilevel(mode, J, R, C):
+    h = fl.cdf97()
+    n = wv.layout(R, C, 10, mode, J)[0]
+    Wm = wv.dense(lambda x: wv.W(x, h, mode, J, R, C), n)
+    Wa = wv.dense(lambda y: wv.W_adj(y, h, mode, J), R * C, (R, C))
+    Wp = wv.dense(lambda y: wv.W_pinv(y, h, mode, J), R * C, (R, C))
+    Wpa = wv.dense(lambda x: wv.W_pinv_adj(x, h, mode, J, R, C), n)
+    np.testing.assert_allclose(Wa, Wm.T, atol=1e-13)
+    np.testing.assert_allclose(Wpa, Wp.T, atol=1e-13)
+    np.testing.assert_allclose(Wm @ Wp, np.eye(R * C), atol=1e-11)
+    assert np.abs(Wa - Wp).max() > 1e-2
