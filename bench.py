@@ -259,6 +259,65 @@ def bench_warm(torch, ops, n_images: int) -> dict:
     return s
 
 
+def graph_us(torch, stream, fn, name: str, reps: int = 50) -> float:
+    """Average us of one call of fn (library launches on `stream`), from a
+    captured graph of `reps` calls replayed 4 times, HIP events on the stream."""
+    for _ in range(3):
+        assert fn() == 0, name
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(4):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / (4 * reps)
+
+
+def bench_modes(torch, ops, lib, bsp, b, lam: float, modes, steps: int = 100) -> dict:
+    """The same 2048^2 workload with the other boundary modes: FISTA step
+    time and Mpix/s, and A, A^* per application."""
+    import ctypes
+
+    N = b.shape[-1]
+    out = {}
+    for bc in modes:
+        w = ops.WaveletSpec(N, N, 4, taps=8, bc=bc)
+        st = ops.FistaState(w, bsp, b)
+        for _ in range(10):
+            ops.fista_step(st, b, lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ops.fista_step(st, b, lam)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        x = torch.randn(w.ncoef, device=b.device) * 1e-2
+        oi = torch.empty(N, N, device=b.device)
+        oc = torch.empty(w.ncoef, device=b.device)
+        wsn = ops.workspace_bytes(w, bsp, torch.float32, 1)
+        ws = torch.empty(wsn, dtype=torch.uint8, device=b.device)
+        stream = torch.cuda.Stream(device=b.device)
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        P = ops._ptr
+        with torch.cuda.stream(stream):
+            a_us = graph_us(torch, stream, lambda: lib.aw_apply_A(
+                w.c, bsp.c, 0, 1, P(x), P(oi), P(ws), wsn, sp), "A")
+            at_us = graph_us(torch, stream, lambda: lib.aw_apply_A_adjoint(
+                w.c, bsp.c, 0, 1, P(b), P(oc), P(ws), wsn, sp), "A*")
+        out[bc] = {"ncoef": w.ncoef, "ms_per_step": round(ms, 4),
+                   "mpix_s": round(N * N / (ms * 1e-3) / 1e6, 1),
+                   "A_us": round(a_us, 3), "A*_us": round(at_us, 3)}
+        del st, x, oi, oc, ws
+    return out
+
+
 def bench_adjoint_study() -> dict:
     """True adjoint W^* against W^dagger in the FISTA gradient, the paper's
     setting (three-level transform, sym, lambda = 2e-5, 2500 iterations) on a
@@ -266,8 +325,10 @@ def bench_adjoint_study() -> dict:
     from paper_1707_02018_amd import adjoint_study
 
     out = {}
-    for taps, name in ((2, "haar_J3_sym"), (8, "db4_J3_sym")):
-        r = adjoint_study.run(256, 256, taps, 3, "sym", 2.0, 4, 2e-5, 2500, every=500)
+    for taps, fam, name in ((2, "daubechies", "haar_J3_sym"), (8, "daubechies", "db4_J3_sym"),
+                            (10, "cdf97", "cdf97_J3_sym")):
+        r = adjoint_study.run(256, 256, taps, 3, "sym", 2.0, 4, 2e-5, 2500, every=500,
+                              family=fam)
         out[name] = {"blurred": {k: round(v, 6) for k, v in r["blurred"].items()},
                      **{g: {k: round(r[g][k], 6)
                             for k in ("rel_err", "nonzero_pct", "ssim", "objective")}
@@ -385,27 +446,9 @@ def main():
             "W_level1": lambda: lib.wavelet_synth(w1.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
         }
 
-    reps = 50
-    op_us = {}
     with torch.cuda.stream(stream):
         calls = make_calls(stream)
-        for name, fn in calls.items():
-            for _ in range(3):
-                assert fn() == 0, name
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=stream):
-                for _ in range(reps):
-                    fn()
-            g.replay()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(4):
-                g.replay()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            op_us[name] = 1e3 * e0.elapsed_time(e1) / (4 * reps)
+        op_us = {name: graph_us(torch, stream, fn, name) for name, fn in calls.items()}
     ops_mpix = {k: round(npix / v, 1) for k, v in op_us.items()}
 
     # dominant single-kernel operator: level-1 analysis (W^* at level 1) or R / R^*
@@ -446,6 +489,9 @@ def main():
     if not args.no_extras:
         del st
         torch.cuda.empty_cache()
+        log("other boundary modes")
+        extras["other_modes"] = bench_modes(torch, ops, lib, bsp, b, lam,
+                                            [m for m in ("per", "zpd", "sym") if m != args.bc])
         log("batched uneven FISTA")
         extras["batched_uneven_fista"] = bench_batched(torch, ops, args.batched_iters)
         torch.cuda.empty_cache()

@@ -66,17 +66,26 @@ typedef enum { AW_BC_ZPD = 0, AW_BC_SYM = 1, AW_BC_PER = 2, AW_BC_PER_EXT = 3 } 
 #define AW_MAX_LEVELS 8
 #define AW_MAX_RADIUS 12
 
-/* Multi-level 2-D orthogonal wavelet transform of a rows x cols image.
- * lo[0..filter_len) is the reconstruction low-pass filter h (orthonormal even
- * shifts, sum sqrt(2)); the high-pass is g[k] = (-1)^k h[L-1-k].
- * filter_len must be 2, 8 or 16 (Haar, Daubechies-4, Daubechies-8);
- * 1 <= levels <= AW_MAX_LEVELS. */
+/* Multi-level 2-D wavelet transform of a rows x cols image.
+ * Orthogonal (biorthogonal = 0): lo[0..filter_len) is the reconstruction
+ * low-pass filter h (orthonormal even shifts, sum sqrt(2)); the high-pass is
+ * g[k] = (-1)^k h[L-1-k]; every operator uses (h, g).
+ * Biorthogonal (biorthogonal = 1, Sec. "The adjoint for biorthogonal
+ * wavelets"): lo is the synthesis low-pass h_s and lo_analysis the analysis
+ * low-pass h_a (sum_k h_s[k] h_a[k+2m] = delta_m); W and its true adjoint W^*
+ * use (h_s, g_s) with g_s[k] = (-1)^k h_a[L-1-k], so W^* = W~^dagger_zpd
+ * (E^dagger)^* (eq. 4) analyses with the dual filters; W^dagger and
+ * (W^dagger)^* use (h_a, g_a) with g_a[k] = (-1)^k h_s[L-1-k].
+ * filter_len must be 2, 8, 10 or 16 (Haar, Daubechies-4, CDF 9/7 or
+ * Daubechies-5, Daubechies-8); 1 <= levels <= AW_MAX_LEVELS. */
 typedef struct {
   int32_t rows, cols;
   int32_t levels;
   int32_t filter_len;
   int32_t bc; /* aw_bc */
   double lo[AW_MAX_TAPS];
+  int32_t biorthogonal;
+  double lo_analysis[AW_MAX_TAPS];
 } aw_wavelet;
 
 /* Separable blur R with half-point reflexive boundaries (Sec. "Example 1"):
@@ -98,6 +107,14 @@ const char* aw_last_error(void);
  * doubles to lo_out, sum sqrt(2)). Sec. "The adjoint for orthogonal wavelets"
  * names Haar and Daubechies wavelets. */
 aw_status aw_daubechies(int32_t taps, double* lo_out);
+
+/* Biorthogonal CDF 9/7 low-pass pair as length-10 filters (host
+ * computation): the p = 4 product filter 2 cos^8(w/2) P(sin^2(w/2)) split
+ * into the 7-tap synthesis filter (the real root of P) and the 9-tap analysis
+ * filter (the complex pair), both symmetric about index 4 (synthesis taps at
+ * 1..7, analysis taps at 0..8), each summing to sqrt(2). Sec. "The adjoint for
+ * biorthogonal wavelets" runs its second experiment with this pair. */
+aw_status aw_cdf97(double* lo_syn_out, double* lo_ana_out);
 
 /* Normalised Gaussian PSF taps g[u] ~ exp(-u^2/(2 sigma^2)), |u| <= radius
  * (host computation; writes 2*radius+1 doubles). */

@@ -23,7 +23,8 @@ BC = {"zpd": 0, "sym": 1, "per": 2, "per_ext": 3}
 class Wavelet(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("filter_len", ctypes.c_int32), ("bc", ctypes.c_int32),
-                ("lo", ctypes.c_double * MAX_TAPS)]
+                ("lo", ctypes.c_double * MAX_TAPS), ("biorthogonal", ctypes.c_int32),
+                ("lo_analysis", ctypes.c_double * MAX_TAPS)]
 
 
 class Blur(ctypes.Structure):
@@ -45,6 +46,7 @@ _i32, _i64, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.
 # name -> (argtypes); every entry point returns aw_status (int) except aw_last_error
 SIGNATURES = {
     "aw_daubechies": [_i32, ctypes.POINTER(_dbl)],
+    "aw_cdf97": [ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     "aw_gaussian_psf": [_dbl, _i32, ctypes.POINTER(_dbl)],
     "aw_wavelet_layout": [_W, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "aw_workspace_size": [_W, _B, _i32, _i32, ctypes.POINTER(_sz)],

@@ -7,7 +7,8 @@ the place of W^*, and compares the reconstructions by their relative error
 against the unblurred image and their share of nonzero coefficients; for its
 biorthogonal case it adds the structural similarity (SSIM) over the
 iterations. This module runs the same comparison on the library's fista_step
-(the gradient map is a flag of the FISTA state) for any orthogonal filter.
+(the gradient map is a flag of the FISTA state) for the orthogonal Daubechies
+filters and the biorthogonal CDF 9/7 pair.
 
 The paper's test image is a resolution chart that is not available here: the
 rectangle-plus-gradient generator stands in for it, blurred by the reflexive
@@ -76,14 +77,16 @@ def measures(w: ops.WaveletSpec, bsp: ops.BlurSpec, b, x, lam: float, img: np.nd
 
 def run(rows: int = 256, cols: int = 256, taps: int = 2, levels: int = 3, bc: str = "sym",
         sigma: float = 2.0, radius: int = 4, lam: float = 2e-5, iters: int = 2500,
-        every: int = 250, seed: int = 0, device="cuda:0") -> dict:
+        every: int = 250, seed: int = 0, device="cuda:0", family: str = "daubechies") -> dict:
     """FISTA from zero with each gradient map; measures at every `every`-th
-    iteration and at the last."""
+    iteration and at the last. family="cdf97" runs the biorthogonal CDF 9/7
+    pair (taps is then ignored)."""
     import torch
 
-    w = ops.WaveletSpec(rows, cols, levels, taps=taps, bc=bc)
+    w = ops.WaveletSpec(rows, cols, levels, taps=taps, bc=bc, family=family)
     img, b, bsp = make_problem(rows, cols, sigma, radius, seed, device)
-    out = {"config": {"rows": rows, "cols": cols, "taps": taps, "levels": levels, "bc": bc,
+    out = {"config": {"rows": rows, "cols": cols, "family": family, "taps": w.taps,
+                      "levels": levels, "bc": bc,
                       "sigma": sigma, "radius": radius, "lambda": lam, "iterations": iters,
                       "seed": seed}}
     blurred = b.double().cpu().numpy()
@@ -107,6 +110,7 @@ def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--taps", type=int, default=2)
+    ap.add_argument("--family", default="daubechies", choices=["daubechies", "cdf97"])
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--bc", default="sym")
     ap.add_argument("--sigma", type=float, default=2.0)
@@ -117,7 +121,7 @@ def main(argv=None) -> None:
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
     res = run(a.size, a.size, a.taps, a.levels, a.bc, a.sigma, a.radius, a.lam, a.iters, a.every,
-              a.seed)
+              a.seed, family=a.family)
     print(json.dumps(res))
 
 

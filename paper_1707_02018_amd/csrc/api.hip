@@ -49,7 +49,13 @@ struct WavePlan {
   int sr[AW_MAX_LEVELS + 1] = {0}, sc[AW_MAX_LEVELS + 1] = {0};
   long long ncoef = 0;
   long long off_hvd[AW_MAX_LEVELS + 1] = {0};  // offset of H_j in the coefficient vector
-  double lo[AW_MAX_TAPS] = {0};
+  bool bior = false;
+  // tap sources of the two sides (low-pass | low-pass whose alternating flip
+  // is the high-pass): W and W^* use syn, W^dagger and (W^dagger)^* use ana
+  double syn[2 * AW_MAX_TAPS] = {0};
+  double ana[2 * AW_MAX_TAPS] = {0};
+  // fold weights 1/mult (pinv = 1: W, W^*) or 1 (pinv = 0: W^dagger, its adjoint)
+  const double* taps(int pinv) const { return pinv ? syn : ana; }
 };
 
 int coef_len(int N, int L, int bc, int e) {
@@ -62,8 +68,10 @@ aw_status make_plan(const aw_wavelet* w, WavePlan& p) {
   if (w->rows < 1 || w->cols < 1) return fail(AW_EINVAL, "image size %dx%d", w->rows, w->cols);
   if (w->levels < 1 || w->levels > AW_MAX_LEVELS)
     return fail(AW_EINVAL, "levels=%d outside [1, %d]", w->levels, AW_MAX_LEVELS);
-  if (w->filter_len != 2 && w->filter_len != 8 && w->filter_len != 16)
-    return fail(AW_EINVAL, "filter_len=%d (supported: 2, 8, 16)", w->filter_len);
+  if (w->filter_len != 2 && w->filter_len != 8 && w->filter_len != 10 && w->filter_len != 16)
+    return fail(AW_EINVAL, "filter_len=%d (supported: 2, 8, 10, 16)", w->filter_len);
+  if (w->biorthogonal != 0 && w->biorthogonal != 1)
+    return fail(AW_EINVAL, "biorthogonal=%d", w->biorthogonal);
   if (w->bc < AW_BC_ZPD || w->bc > AW_BC_PER_EXT) return fail(AW_EINVAL, "bc=%d", w->bc);
   p.J = w->levels;
   p.L = w->filter_len;
@@ -71,15 +79,28 @@ aw_status make_plan(const aw_wavelet* w, WavePlan& p) {
   p.e = (p.bc == aw::SYM || p.bc == aw::PER_EXT) ? p.L - 1 : 0;
   p.rows = w->rows;
   p.cols = w->cols;
+  p.bior = w->biorthogonal == 1;
+  const double* hs = w->lo;
+  const double* ha = p.bior ? w->lo_analysis : w->lo;
   for (int k = 0; k < p.L; ++k) {
-    if (!std::isfinite(w->lo[k])) return fail(AW_EINVAL, "filter tap %d is not finite", k);
-    p.lo[k] = w->lo[k];
+    if (!std::isfinite(hs[k]) || !std::isfinite(ha[k]))
+      return fail(AW_EINVAL, "filter tap %d is not finite", k);
   }
-  for (int m = 0; m < p.L / 2; ++m) {  // orthonormal even shifts
+  // orthonormal (h = h_s = h_a) or biorthogonal even shifts:
+  // sum_k h_s[k] h_a[k + 2m] = delta_m for every shift
+  for (int m = -(p.L / 2 - 1); m <= p.L / 2 - 1; ++m) {
     double s = 0.0;
-    for (int k = 0; k + 2 * m < p.L; ++k) s += p.lo[k] * p.lo[k + 2 * m];
+    for (int k = 0; k < p.L; ++k)
+      if (k + 2 * m >= 0 && k + 2 * m < p.L) s += hs[k] * ha[k + 2 * m];
     if (std::fabs(s - (m == 0 ? 1.0 : 0.0)) > 1e-12)
-      return fail(AW_EINVAL, "filter is not orthonormal (shift %d: %.3e)", 2 * m, s);
+      return fail(AW_EINVAL, "filter %s (shift %d: %.3e)",
+                  p.bior ? "pair is not biorthogonal" : "is not orthonormal", 2 * m, s);
+  }
+  for (int k = 0; k < p.L; ++k) {
+    p.syn[k] = hs[k];
+    p.syn[AW_MAX_TAPS + k] = ha[k];
+    p.ana[k] = ha[k];
+    p.ana[AW_MAX_TAPS + k] = hs[k];
   }
   p.sr[0] = p.rows;
   p.sc[0] = p.cols;
@@ -227,7 +248,7 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
   }
   for (int j = p.J; j >= j_lo; --j) {
     if (chain_top && j == chain_top) {
-      hipError_t e = aw::launch_synth_chain(p.L, p.lo, ch, chain_lds, batch, s);
+      hipError_t e = aw::launch_synth_chain(p.L, p.taps(pinv), ch, chain_lds, batch, s);
       if (e != hipSuccess) return hip_check(e, "synthesis launch");
       j = 2;  // levels chain_top .. 2 done
       continue;
@@ -249,7 +270,7 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
       z.stride_out = (long long)z.r.N * z.c.N;
       if (aw::synth_level_lds(dtype, p.L, z) > 160 * 1024)
         return fail(AW_EUNSUPPORTED, "tile window exceeds LDS at level %d", j);
-      e = aw::launch_synth_level(dtype, p.L, p.lo, z, batch, s);
+      e = aw::launch_synth_level(dtype, p.L, p.taps(pinv), z, batch, s);
       if (e != hipSuccess) return hip_check(e, "synthesis launch");
       aw::FoldLevel f{};
       f.ext = z.out;
@@ -265,7 +286,7 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
     } else {
       if (aw::synth_level_lds(dtype, p.L, d) > 160 * 1024)
         return fail(AW_EUNSUPPORTED, "tile window exceeds LDS at level %d", j);
-      e = aw::launch_synth_level(dtype, p.L, p.lo, d, batch, s);
+      e = aw::launch_synth_level(dtype, p.L, p.taps(pinv), d, batch, s);
       if (e != hipSuccess) return hip_check(e, "synthesis launch");
     }
   }
@@ -304,7 +325,7 @@ aw_status run_analysis(const WavePlan& p, aw_dtype dt, int batch, const void* im
     d.c = {p.sc[j - 1], p.sc[j], p.e};
     d.bc = p.bc;
     d.pinv = pinv;
-    hipError_t e = aw::launch_ana_level(dt == AW_F64, p.L, p.lo, d, batch, s);
+    hipError_t e = aw::launch_ana_level(dt == AW_F64, p.L, p.taps(pinv), d, batch, s);
     if (e != hipSuccess) return hip_check(e, "analysis launch");
   }
   return AW_OK;
@@ -341,7 +362,7 @@ aw_status run_analysis_prox(const WavePlan& p, aw_dtype dt, int batch, const voi
     pe.pbase = pbase;
     pe.pstride = l.n_pt;
     pbase += aw::ana_level_tiles(dt == AW_F64, d, batch);
-    hipError_t e = aw::launch_ana_level_prox(dt == AW_F64, p.L, p.lo, d, pe, batch, s);
+    hipError_t e = aw::launch_ana_level_prox(dt == AW_F64, p.L, p.taps(pinv), d, pe, batch, s);
     if (e != hipSuccess) return hip_check(e, "analysis launch");
   }
   return AW_OK;
@@ -427,6 +448,47 @@ aw_status aw_daubechies(int32_t taps, double* lo_out) {
   double sum = 0.0;
   for (int k = 0; k < taps; ++k) sum += poly[k].real();
   for (int k = 0; k < taps; ++k) lo_out[k] = poly[k].real() * std::sqrt(2.0) / sum;
+  return ok();
+}
+
+aw_status aw_cdf97(double* lo_syn_out, double* lo_ana_out) {
+  if (!lo_syn_out || !lo_ana_out) return fail(AW_EINVAL, "output pointer is NULL");
+  // P(y) = 1 + 4y + 10y^2 + 20y^3 is increasing (P' > 0), so it has one real
+  // root: Newton from 0, then the quadratic factor holds the complex pair
+  double y1 = 0.0;
+  for (int it = 0; it < 100; ++it) {
+    const double f = ((20.0 * y1 + 10.0) * y1 + 4.0) * y1 + 1.0;
+    const double df = (60.0 * y1 + 20.0) * y1 + 4.0;
+    const double step = f / df;
+    y1 -= step;
+    if (std::fabs(step) < 1e-17) break;
+  }
+  const double qb = 10.0 + 20.0 * y1, qc = 4.0 + qb * y1;  // P = (y - y1)(20y^2 + qb y + qc)
+  const std::complex<double> y2 =
+      (-qb + std::sqrt(std::complex<double>(qb * qb - 80.0 * qc, 0.0))) / 40.0;
+  const double A = 2.0 * (1.0 / y2).real();  // (1 - y/y2)(1 - y/y3) = 1 - A y + B y^2
+  const double B = 1.0 / std::norm(y2);
+  // centred taps (index = power of z + half-width) of symmetric Laurent polynomials
+  auto conv = [](const std::vector<double>& a, const std::vector<double>& b) {
+    std::vector<double> c(a.size() + b.size() - 1, 0.0);
+    for (size_t i = 0; i < a.size(); ++i)
+      for (size_t k = 0; k < b.size(); ++k) c[i + k] += a[i] * b[k];
+    return c;
+  };
+  const std::vector<double> c2 = {0.25, 0.5, 0.25};   // cos^2(w/2)
+  const std::vector<double> s2 = {-0.25, 0.5, -0.25}; // sin^2(w/2)
+  const std::vector<double> c4 = conv(c2, c2);
+  std::vector<double> f1 = {-s2[0] / y1, 1.0 - s2[1] / y1, -s2[2] / y1};
+  const std::vector<double> s4 = conv(s2, s2);
+  std::vector<double> f2(5, 0.0);
+  f2[2] = 1.0;
+  for (int k = 0; k < 3; ++k) f2[k + 1] -= A * s2[k];
+  for (int k = 0; k < 5; ++k) f2[k] += B * s4[k];
+  const std::vector<double> hs = conv(c4, f1);  // 7 taps
+  const std::vector<double> ha = conv(c4, f2);  // 9 taps
+  for (int k = 0; k < 10; ++k) lo_syn_out[k] = lo_ana_out[k] = 0.0;
+  for (int k = 0; k < 7; ++k) lo_syn_out[1 + k] = std::sqrt(2.0) * hs[k];
+  for (int k = 0; k < 9; ++k) lo_ana_out[k] = std::sqrt(2.0) * ha[k];
   return ok();
 }
 
@@ -593,7 +655,7 @@ aw_status aw_apply_A_fused(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype
                 "radius + 1 (and, for sym, L - 1) samples per axis and a window within LDS");
   hipStream_t s = (hipStream_t)stream;
   if ((st = run_synthesis(p, dtype, batch, coef, img, workspace, l, 1, s, 2)) != AW_OK) return st;
-  st = hip_check(aw::launch_synth_blur(p.L, p.lo, d1, d, b_obs, img, batch, s),
+  st = hip_check(aw::launch_synth_blur(p.L, p.taps(1), d1, d, b_obs, img, batch, s),
                  "fused synthesis-blur launch");
   return st == AW_OK ? ok() : st;
 }
@@ -630,7 +692,7 @@ aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dty
                 "fused A^* needs zpd or sym, filter length 2, 8 or 16 and, for sym, images of "
                 "at least L - 1 samples per axis");
   hipStream_t s = (hipStream_t)stream;
-  st = hip_check(aw::launch_blur_ana(p.L, p.lo, d1, d, batch, s), "fused blur-analysis launch");
+  st = hip_check(aw::launch_blur_ana(p.L, p.taps(1), d1, d, batch, s), "fused blur-analysis launch");
   if (st != AW_OK) return st;
   st = run_analysis(p, dtype, batch, img, coef, workspace, l, 1, s, 2);
   return st == AW_OK ? ok() : st;

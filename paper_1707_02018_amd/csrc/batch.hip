@@ -81,6 +81,7 @@ size_t alignb(size_t x) { return (x + kAlignB - 1) / kAlignB * kAlignB; }
 
 struct Image {
   aw_wavelet w;
+  double taps[2 * AW_MAX_TAPS];  // tap source of make_taps: the low-pass in both halves
   aw::BlurDesc b;
   int J, L, bc, e, rows, cols;
   int sr[AW_MAX_LEVELS + 1], sc[AW_MAX_LEVELS + 1];
@@ -145,9 +146,12 @@ aw_status image_setup(const aw_wavelet& w, const aw_blur& b, Image& im) {
   aw_status st = aw_wavelet_layout(&w, &n, sr, sc);
   if (st != AW_OK) return bfail(st, aw_last_error());
   if (w.bc == AW_BC_PER_EXT) return bfail(AW_EUNSUPPORTED, "batched path: periodic extension not supported");
+  if (w.biorthogonal || w.filter_len == 10)
+    return bfail(AW_EUNSUPPORTED, "batched path: orthogonal filters of length 2, 8 or 16 only");
   if (b.rows != w.rows || b.cols != w.cols) return bfail(AW_EINVAL, "wavelet and blur sizes differ");
   if (b.radius < 0 || b.radius > AW_MAX_RADIUS) return bfail(AW_EINVAL, "radius out of range");
   im.w = w;
+  for (int k = 0; k < AW_MAX_TAPS; ++k) im.taps[k] = im.taps[AW_MAX_TAPS + k] = w.lo[k];
   im.J = w.levels;
   im.L = w.filter_len;
   im.bc = w.bc;
@@ -300,7 +304,7 @@ aw_status build(aw_batch* p) {
       d.c = {im.sc[j - 1], im.sc[j], im.e};
       d.bc = im.bc;
       d.pinv = 1;
-      aw::make_synth_item(0, d, im.w.lo, im.L, i, buf.data());
+      aw::make_synth_item(0, d, im.taps, im.L, i, buf.data());
       Group& g = group_for(st, 0, im.L, im.bc);
       add_item(g, buf.data(), aw::synth_item_size(0), aw::synth_tiles(0, p->var[0], d));
       g.lds = std::max(g.lds, aw::synth_item_lds(0, im.L, p->var[0], d));
@@ -363,7 +367,7 @@ aw_status build(aw_batch* p) {
       pe.beta_len = kBetaLen;
       const int tiles = aw::ana_tiles(0, p->var[1], d);
       lvl_base[i] += tiles;
-      aw::make_ana_item_prox(d, im.w.lo, im.L, i, pe, buf.data());
+      aw::make_ana_item_prox(d, im.taps, im.L, i, pe, buf.data());
       Group& g = group_for(st, 1, im.L, im.bc);
       add_item(g, buf.data(), aw::ana_item_size(0), tiles);
     }

@@ -34,12 +34,16 @@ struct Vec<double> {
   using V4 = double4;
 };
 
+// Taps of one side of a transform: the low-pass h = src[0..L) and the
+// high-pass g[k] = (-1)^k f[L-1-k] with f = src[kMaxTaps..kMaxTaps+L) (h
+// itself for orthogonal filters, the other side's low-pass for a
+// biorthogonal pair).
 template <typename T>
-static Taps<T> make_taps(const double* lo, int L) {
+static Taps<T> make_taps(const double* src, int L) {
   Taps<T> t{};
   for (int k = 0; k < L; ++k) {
-    t.h[k] = (T)lo[k];
-    t.g[k] = (T)(((k & 1) ? -1.0 : 1.0) * lo[L - 1 - k]);
+    t.h[k] = (T)src[k];
+    t.g[k] = (T)(((k & 1) ? -1.0 : 1.0) * src[kMaxTaps + L - 1 - k]);
   }
   return t;
 }

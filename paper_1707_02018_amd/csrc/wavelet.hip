@@ -111,6 +111,7 @@ static hipError_t launch_synth_L(int L, const double* lo, const SynthLevel& d, i
   switch (L) {
     case 2: return launch_synth_bc<T, 2>(lo, d, batch, s);
     case 8: return launch_synth_bc<T, 8>(lo, d, batch, s);
+    case 10: return launch_synth_bc<T, 10>(lo, d, batch, s);
     case 16: return launch_synth_bc<T, 16>(lo, d, batch, s);
     default: return hipErrorInvalidValue;
   }
@@ -215,11 +216,17 @@ size_t synth_chain_plan(int dtype, int L, SynthChain& c) {
   }
   size_t lds = 0;
   if (bc == SYM) {
-    lds = L == 2 ? chain_plan_t<2, SYM>(c) : L == 8 ? chain_plan_t<8, SYM>(c)
-                                                    : L == 16 ? chain_plan_t<16, SYM>(c) : 0;
+    lds = L == 2    ? chain_plan_t<2, SYM>(c)
+          : L == 8  ? chain_plan_t<8, SYM>(c)
+          : L == 10 ? chain_plan_t<10, SYM>(c)
+          : L == 16 ? chain_plan_t<16, SYM>(c)
+                    : 0;
   } else if (bc == ZPD) {
-    lds = L == 2 ? chain_plan_t<2, ZPD>(c) : L == 8 ? chain_plan_t<8, ZPD>(c)
-                                                    : L == 16 ? chain_plan_t<16, ZPD>(c) : 0;
+    lds = L == 2    ? chain_plan_t<2, ZPD>(c)
+          : L == 8  ? chain_plan_t<8, ZPD>(c)
+          : L == 10 ? chain_plan_t<10, ZPD>(c)
+          : L == 16 ? chain_plan_t<16, ZPD>(c)
+                    : 0;
   }
   return lds <= 64 * 1024 ? lds : 0;
 }
@@ -243,6 +250,8 @@ hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size
                              : launch_chain_t<2, ZPD>(lo, c, lds, batch, s);
     case 8: return bc == SYM ? launch_chain_t<8, SYM>(lo, c, lds, batch, s)
                              : launch_chain_t<8, ZPD>(lo, c, lds, batch, s);
+    case 10: return bc == SYM ? launch_chain_t<10, SYM>(lo, c, lds, batch, s)
+                              : launch_chain_t<10, ZPD>(lo, c, lds, batch, s);
     case 16: return bc == SYM ? launch_chain_t<16, SYM>(lo, c, lds, batch, s)
                               : launch_chain_t<16, ZPD>(lo, c, lds, batch, s);
     default: return hipErrorInvalidValue;
@@ -324,6 +333,7 @@ static hipError_t launch_ana_L(int L, const double* lo, const AnaLevel& d, int b
   switch (L) {
     case 2: return launch_ana_bc<T, 2>(lo, d, batch, s);
     case 8: return launch_ana_bc<T, 8>(lo, d, batch, s);
+    case 10: return launch_ana_bc<T, 10>(lo, d, batch, s);
     case 16: return launch_ana_bc<T, 16>(lo, d, batch, s);
     default: return hipErrorInvalidValue;
   }
@@ -370,6 +380,7 @@ static hipError_t launch_ana_prox_L(int L, const double* lo, const AnaLevel& d, 
   switch (L) {
     case 2: return launch_ana_prox_bc<T, 2>(lo, d, pe, batch, s);
     case 8: return launch_ana_prox_bc<T, 8>(lo, d, pe, batch, s);
+    case 10: return launch_ana_prox_bc<T, 10>(lo, d, pe, batch, s);
     case 16: return launch_ana_prox_bc<T, 16>(lo, d, pe, batch, s);
     default: return hipErrorInvalidValue;
   }

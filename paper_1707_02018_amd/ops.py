@@ -24,6 +24,13 @@ def daubechies(taps: int) -> np.ndarray:
     return np.array(out[:], dtype=np.float64)
 
 
+def cdf97() -> tuple[np.ndarray, np.ndarray]:
+    """Biorthogonal CDF 9/7 low-pass pair (synthesis, analysis), length 10."""
+    hs, ha = (ctypes.c_double * 10)(), (ctypes.c_double * 10)()
+    check("aw_cdf97", load().aw_cdf97(hs, ha))
+    return np.array(hs[:], dtype=np.float64), np.array(ha[:], dtype=np.float64)
+
+
 def gaussian_psf(sigma: float, radius: int) -> np.ndarray:
     out = (ctypes.c_double * (2 * radius + 1))()
     check("aw_gaussian_psf", load().aw_gaussian_psf(float(sigma), int(radius), out))
@@ -32,18 +39,27 @@ def gaussian_psf(sigma: float, radius: int) -> np.ndarray:
 
 @dataclass
 class WaveletSpec:
-    """Multi-level 2-D orthogonal wavelet transform of a rows x cols image."""
+    """Multi-level 2-D wavelet transform of a rows x cols image: orthogonal
+    Daubechies filters of `taps` taps (or the low-pass `lo`), or, with
+    family="cdf97" (or `lo_analysis` given), a biorthogonal pair whose
+    synthesis low-pass is `lo` and analysis low-pass `lo_analysis`."""
     rows: int
     cols: int
     levels: int
     taps: int = 8
     bc: str = "sym"
     lo: np.ndarray | None = None
+    lo_analysis: np.ndarray | None = None
+    family: str = "daubechies"
     _c: _lib.Wavelet = field(init=False, repr=False)
 
     def __post_init__(self):
         if self.bc not in _lib.BC:
             raise ValueError(f"bc must be one of {BC_NAMES}")
+        if self.family == "cdf97":
+            self.lo, self.lo_analysis = cdf97()
+        elif self.family != "daubechies":
+            raise ValueError("family must be 'daubechies' or 'cdf97'")
         if self.lo is None:
             self.lo = daubechies(self.taps)
         self.lo = np.asarray(self.lo, dtype=np.float64)
@@ -53,7 +69,19 @@ class WaveletSpec:
         c.bc = _lib.BC[self.bc]
         for k, v in enumerate(self.lo):
             c.lo[k] = float(v)
+        if self.lo_analysis is not None:
+            self.lo_analysis = np.asarray(self.lo_analysis, dtype=np.float64)
+            if len(self.lo_analysis) != self.taps:
+                raise ValueError("lo and lo_analysis must have the same length")
+            c.biorthogonal = 1
+            for k, v in enumerate(self.lo_analysis):
+                c.lo_analysis[k] = float(v)
         self._c = c
+
+    @property
+    def filters(self):
+        """The oracle's filter argument: lo, or the pair (lo, lo_analysis)."""
+        return self.lo if self.lo_analysis is None else (self.lo, self.lo_analysis)
 
     @property
     def c(self):

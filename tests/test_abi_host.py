@@ -190,3 +190,46 @@ def test_cnn_entry_points_validate(lib):
     assert lib.aw_sq_error(10, d, d, 1.0, None, d, d, 0, None) == _lib.EINVAL  # ws too small
     n = ctypes.c_size_t()
     assert lib.aw_sq_error_workspace(100000, ctypes.byref(n)) == _lib.OK and n.value >= 8
+
+
+def test_cdf97_matches_oracle(lib):
+    """The native CDF 9/7 construction against the oracle's (independent code
+    of the same factorisation)."""
+    hs, ha = (ctypes.c_double * 10)(), (ctypes.c_double * 10)()
+    assert lib.aw_cdf97(hs, ha) == _lib.OK
+    ref_s, ref_a = ofl.cdf97()
+    np.testing.assert_allclose(np.array(hs[:]), ref_s, atol=1e-15)
+    np.testing.assert_allclose(np.array(ha[:]), ref_a, atol=1e-15)
+    assert lib.aw_cdf97(None, ha) == _lib.EINVAL
+
+
+def _bior(rows=64, cols=64, levels=3, bc=1, hs=None, ha=None, flag=1):
+    ref_s, ref_a = ofl.cdf97()
+    w = _lib.Wavelet()
+    w.rows, w.cols, w.levels, w.filter_len, w.bc = rows, cols, levels, 10, bc
+    for k in range(10):
+        w.lo[k] = float((ref_s if hs is None else hs)[k])
+        w.lo_analysis[k] = float((ref_a if ha is None else ha)[k])
+    w.biorthogonal = flag
+    return w
+
+
+@pytest.mark.parametrize("bc,mode", [(0, "zpd"), (1, "sym"), (2, "per"), (3, "per_ext")])
+def test_biorthogonal_layout_and_validation(lib, bc, mode):
+    for rows, cols, J in [(256, 256, 3), (96, 160, 4), (18, 10, 1)]:
+        if mode == "per" and (rows % 2 ** J or cols % 2 ** J):
+            continue
+        w = _bior(rows, cols, J, bc)
+        n = ctypes.c_int64()
+        sr = (ctypes.c_int32 * (J + 1))()
+        sc = (ctypes.c_int32 * (J + 1))()
+        assert lib.aw_wavelet_layout(ctypes.byref(w), ctypes.byref(n), sr, sc) == _lib.OK
+        ref_n, ref_r, ref_c = owv.layout(rows, cols, 10, mode, J)
+        assert n.value == ref_n and list(sr) == ref_r and list(sc) == ref_c
+    ref_s, ref_a = ofl.cdf97()
+    assert _einval(lib, _bior(flag=0))                    # the pair is not orthonormal
+    assert _einval(lib, _bior(flag=2))
+    assert _einval(lib, _bior(ha=np.roll(ref_a, 1)))      # shifted: not biorthogonal
+    bad = ref_s.copy()
+    bad[4] += 1e-6
+    assert _einval(lib, _bior(hs=bad))

@@ -21,15 +21,16 @@ def _gpu():
         pytest.skip("no GPU visible")
 
 
-@pytest.mark.parametrize("taps", [2, 8])
+@pytest.mark.parametrize("taps", [2, 8, "cdf97"])
 def test_study_measures_match_oracle(taps):
     rows, cols, J, sigma, r, lam, iters = 64, 48, 3, 2.0, 4, 2e-5, 60
     print(f"[study] {rows}x{cols} taps={taps} J={J} {iters} iterations", flush=True)
-    res = adjoint_study.run(rows, cols, taps, J, "sym", sigma, r, lam, iters, every=30,
-                            device=DEV)
+    fam = "cdf97" if taps == "cdf97" else "daubechies"
+    res = adjoint_study.run(rows, cols, 10 if fam == "cdf97" else taps, J, "sym", sigma, r, lam,
+                            iters, every=30, device=DEV, family=fam)
     img, b, bsp = adjoint_study.make_problem(rows, cols, sigma, r, 0, DEV)
     bh = b.double().cpu().numpy()
-    h = ofl.by_taps(taps)
+    h = ofl.cdf97() if fam == "cdf97" else ofl.by_taps(taps)
     prob = ofi.Problem(rows, cols, h, "sym", J, bsp.taps)
     assert abs(res["blurred"]["rel_err"] -
                np.linalg.norm(bh - img) / np.linalg.norm(img)) < 1e-12
