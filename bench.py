@@ -36,7 +36,7 @@ COPY_REF_BYTES = 256 << 20  # read (and again written) by the --copy-reference k
 # Kernels whose HBM traffic the roofline reports: op name -> (kernel name prefix,
 # grid size at 2048^2 db4 J=4, source file whose hash the record carries).
 PMC_KERNELS = {
-    "W_level1": ("void aw::synth_level_kernel<float, 8, 1, 0>", 1048576, "wavelet.hip"),
+    "W_level1": ("void aw::synth_level_kernel<float, 8, 1, 0>", 524288, "wavelet.hip"),
     "W*_level1": ("void aw::ana_level_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
     "R": ("void aw::blur_tile_kernel<float, 7, false, 0>", 524288, "blur.hip"),
     "R*": ("void aw::blur_tile_kernel<float, 7, true, 0>", 524288, "blur.hip"),
