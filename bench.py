@@ -336,6 +336,25 @@ def bench_adjoint_study() -> dict:
     return out
 
 
+def bench_blind() -> dict:
+    """Two-channel blind estimation with the Huber TV term at the paper's sizes
+    (K = 894, N = 1717, guessed 844 / 1767; synthetic sparse channels and an
+    impulsive source, noise 0.005), FP32, up to 10,000 alternating iterations
+    (stopping when the objective stalls), two problem seeds."""
+    from paper_1707_02018_amd import blind
+
+    def rnd(v):
+        if isinstance(v, float):
+            return round(v, 6)
+        if isinstance(v, list):
+            return [round(a, 4) for a in v]
+        if isinstance(v, dict):
+            return {kk: round(vv, 6) for kk, vv in v.items()}
+        return v
+    return {f"seed{sd}": {k: rnd(v) for k, v in blind.run(10000, sd, tol=1e-7).items()}
+            for sd in (0, 1)}
+
+
 def cpu_baseline(size: int, bc: str, iters: int = 2) -> dict:
     """The FP64 NumPy oracle timed on this host (separate process), a bounded
     sample of the same workload: `iters` FISTA iterations at full size."""
@@ -505,6 +524,8 @@ def main():
         extras["warm_start"] = bench_warm(torch, ops, args.warm_images)
         log("adjoint vs pseudoinverse gradient (256^2, 2500 iterations)")
         extras["adjoint_vs_pinv"] = bench_adjoint_study()
+        log("multi-channel blind channel estimation (eq. 7, up to 10,000 iterations)")
+        extras["blind_channel"] = bench_blind()
     log("cpu baseline")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(N, args.bc)

@@ -208,6 +208,42 @@ aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dty
                                    int32_t batch, const void* img, void* coef, void* workspace,
                                    size_t workspace_bytes, void* stream);
 
+/* ------------------------------- multi-channel blind channel estimation */
+
+/* Sec. "Example 2", eq. 7: C channels h_c (length K) observe one source s
+ * (length N); x_c = h_c * s (full linear convolution, length M = K+N-1).
+ * For all channels at once:
+ *   resid[c]        = h_c * s - x_obs[c]   (x_obs NULL: no subtraction)
+ *   grad_h[c]       = S^* resid[c]:  grad_h[c][n] = sum_{k<N} s[k] resid[c][k+n]
+ *   grad_s_parts[c] = H_c^* resid[c]: sum_{k<K} h_c[k] resid[c][k+n]
+ *   grad_s          = sum_c grad_s_parts[c] (channels in order; needs grad_s_parts)
+ *   rnorm[c]        = ||resid[c]||^2 (device doubles)
+ * h [C][K], x_obs and resid [C][M], grad_s_parts [C][N], s and grad_s [N];
+ * grad_h, grad_s_parts, grad_s and rnorm may be NULL. These are the gradients
+ * of 1/2 ||h_c * s - x_c||^2 (the data term of eq. 7 carries no 1/2: its
+ * gradients are twice these). resid must not alias the inputs. */
+aw_status aw_conv_multichannel(aw_dtype dtype, int32_t channels, int32_t K, int32_t N,
+                               const void* h, const void* s, const void* x_obs, void* resid,
+                               void* grad_h, void* grad_s_parts, void* grad_s, double* rnorm,
+                               void* stream);
+
+/* The softened TV term of eq. 7 per row b of h [batch][K]:
+ *   value[b] = sum_{j<K-1} L_delta((D h_b)_j),  (D h)_j = h_{j+1} - h_j,
+ *   L_delta(z) = z^2/2 (|z| <= delta), delta (|z| - delta/2) otherwise,
+ *   grad[b][j] += gscale * (D^* clip(D h_b, -delta, delta))_j,
+ * with (D^* v)_j = v_{j-1} - v_j and v_{-1} = v_{K-1} = 0 (the gradient of
+ * gscale * value). value (device doubles) and grad may be NULL; delta > 0. */
+aw_status aw_huber_tv(aw_dtype dtype, int32_t batch, int32_t K, const void* h, double delta,
+                      double gscale, void* grad, double* value, void* stream);
+
+/* Proximal gradient step for an l1 term: out = soft(x - step g, thresh),
+ * soft(v, t) = sign(v) max(|v| - t, 0), over n entries; stats (device doubles
+ * [3], or NULL) = [sum g (out - x), sum (out - x)^2, sum |out|], the terms of
+ * a backtracking test. out must not alias x or g; step, thresh >= 0. One
+ * workgroup: meant for channel and source vectors, not images. */
+aw_status aw_prox_l1(aw_dtype dtype, int64_t n, const void* x, const void* g, double step,
+                     double thresh, void* out, double* stats, void* stream);
+
 /* ------------------------------------------------------------------ FISTA */
 
 /* State of FISTA (Beck & Teboulle) on eq. (1) for `batch` independent images

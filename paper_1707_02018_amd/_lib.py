@@ -64,6 +64,9 @@ SIGNATURES = {
                    _P],
     "aw_objective": [_W, _B, _i32, _i32, _P, _dbl, _P, _P, _P, _sz, _P],
     "conv_adjoint_pair": [_i32, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _P],
+    "aw_conv_multichannel": [_i32, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "aw_huber_tv": [_i32, _i32, _i32, _P, _dbl, _dbl, _P, _P, _P],
+    "aw_prox_l1": [_i32, _i64, _P, _P, _dbl, _dbl, _P, _P, _P],
     "aw_batch_create": [_i32, _W, _B, ctypes.POINTER(_P)],
     "aw_batch_destroy": [_P],
     "aw_batch_layout": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)],

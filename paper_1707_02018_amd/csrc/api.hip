@@ -805,6 +805,67 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
   return st == AW_OK ? ok() : st;
 }
 
+aw_status aw_conv_multichannel(aw_dtype dtype, int32_t channels, int32_t K, int32_t N,
+                               const void* h, const void* s, const void* x_obs, void* resid,
+                               void* grad_h, void* grad_s_parts, void* grad_s, double* rnorm,
+                               void* stream) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (channels < 1 || K < 1 || N < 1)
+    return fail(AW_EINVAL, "channels=%d K=%d N=%d", channels, K, N);
+  if ((long long)K + N - 1 > (1LL << 31) - 1) return fail(AW_EINVAL, "K+N-1 too large");
+  if (!h || !s || !resid) return fail(AW_EINVAL, "NULL data pointer");
+  if (resid == h || resid == s || resid == x_obs)
+    return fail(AW_EINVAL, "resid must not alias the inputs");
+  if (grad_s && !grad_s_parts)
+    return fail(AW_EINVAL, "grad_s needs grad_s_parts (channels x N scratch)");
+  hipStream_t hs = (hipStream_t)stream;
+  const int di = dtype == AW_F64;
+  st = hip_check(aw::launch_conv_pair(di, channels, K, N, h, s, x_obs, resid, grad_h,
+                                      grad_s_parts, hs, true),
+                 "conv launch");
+  if (st != AW_OK) return st;
+  if (grad_s &&
+      (st = hip_check(aw::launch_sum_rows(di, channels, N, grad_s_parts, grad_s, hs),
+                      "channel sum launch")) != AW_OK)
+    return st;
+  if (rnorm && (st = hip_check(aw::launch_row_sumsq(di, channels, (long long)K + N - 1, resid,
+                                                    rnorm, hs),
+                               "residual norm launch")) != AW_OK)
+    return st;
+  return ok();
+}
+
+aw_status aw_huber_tv(aw_dtype dtype, int32_t batch, int32_t K, const void* h, double delta,
+                      double gscale, void* grad, double* value, void* stream) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (batch < 1 || K < 1) return fail(AW_EINVAL, "batch=%d K=%d", batch, K);
+  if (!h) return fail(AW_EINVAL, "NULL data pointer");
+  if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(gscale))
+    return fail(AW_EINVAL, "delta=%g gscale=%g", delta, gscale);
+  if (grad == h) return fail(AW_EINVAL, "grad must not alias h");
+  st = hip_check(aw::launch_huber_tv(dtype == AW_F64, batch, K, h, delta, gscale, grad, value,
+                                     (hipStream_t)stream),
+                 "huber launch");
+  return st == AW_OK ? ok() : st;
+}
+
+aw_status aw_prox_l1(aw_dtype dtype, int64_t n, const void* x, const void* g, double step,
+                     double thresh, void* out, double* stats, void* stream) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (n < 1) return fail(AW_EINVAL, "n=%lld", (long long)n);
+  if (!x || !g || !out) return fail(AW_EINVAL, "NULL data pointer");
+  if (out == x || out == g) return fail(AW_EINVAL, "out must not alias x or g");
+  if (!(step >= 0.0) || !(thresh >= 0.0) || !std::isfinite(step) || !std::isfinite(thresh))
+    return fail(AW_EINVAL, "step=%g thresh=%g", step, thresh);
+  st = hip_check(aw::launch_prox_l1(dtype == AW_F64, n, x, g, step, thresh, out, stats,
+                                    (hipStream_t)stream),
+                 "prox launch");
+  return st == AW_OK ? ok() : st;
+}
+
 // ------------------------------------------------------- warm-start CNN
 static aw_status cnn_shape(int32_t batch, int32_t rows, int32_t cols) {
   if (batch < 1 || rows < 1 || cols < 1)

@@ -366,9 +366,20 @@ hipError_t launch_blur_batch(int dtype, int radius, bool adj, int var, const voi
                              const int* prefix, int n, int total, const int* active,
                              hipStream_t s);
 
+// shared_s: every pair reads the one signal s (multi-channel blind estimation)
 hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, const void* s,
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
-                            hipStream_t st);
+                            hipStream_t st, bool shared_s = false);
+
+// Multi-channel blind channel estimation helpers (blind.hip).
+hipError_t launch_sum_rows(int dtype, int rows, long long n, const void* in, void* out,
+                           hipStream_t s);
+hipError_t launch_row_sumsq(int dtype, int rows, long long n, const void* x, double* out,
+                            hipStream_t s);
+hipError_t launch_huber_tv(int dtype, int batch, int K, const void* h, double delta,
+                           double gscale, void* grad, double* value, hipStream_t s);
+hipError_t launch_prox_l1(int dtype, long long n, const void* x, const void* g, double step,
+                          double thresh, void* out, double* stats, hipStream_t s);
 
 // ------------------------------------------------------ XCD-aware tile order
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with

@@ -19,9 +19,11 @@ constexpr int kConvOut = 8;                              // outputs per thread
 constexpr int kConvTile = kConvThreads * kConvOut;       // outputs per block
 constexpr int kConvKC = 256;                             // filter taps per LDS chunk
 
-// y[t] = sum_k h[k] x[t - k] - sub[t], t < T (x zero outside [0, nx))
+// y[t] = sum_k h[k] x[t - k] - sub[t], t < T (x zero outside [0, nx); pair p
+// reads x + p * x_stride: 0 shares one signal across the batch)
 template <typename T>
 __global__ __launch_bounds__(kConvThreads) void conv_full_kernel(int K, int nx, int Tlen,
+                                                                 long long x_stride,
                                                                  const T* __restrict__ h,
                                                                  const T* __restrict__ x,
                                                                  const T* __restrict__ sub,
@@ -30,7 +32,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_full_kernel(int K, int nx, 
   __shared__ T sx[kConvTile + kConvKC + 8];
   const int pair = blockIdx.y;
   const T* H = h + (long long)pair * K;
-  const T* X = x + (long long)pair * nx;
+  const T* X = x + (long long)pair * x_stride;
   const int t0 = blockIdx.x * kConvTile;
   const int tb = threadIdx.x * kConvOut;
   T acc[kConvOut];
@@ -120,7 +122,8 @@ __global__ __launch_bounds__(kConvThreads) void corr_short_kernel(int K, int N,
   }
 }
 
-// g[n] = sum_{k<N} s[k] r[k + n] for n in a block of 128 lags.
+// g[n] = sum_{k<N} s[k] r[k + n] for n in a block of 128 lags (pair p reads
+// s + p * s_stride).
 constexpr int kLagThreads = 512;
 constexpr int kLagGroups = 16;                          // 8 lags each -> 128 lags
 constexpr int kLagSlices = kLagThreads / kLagGroups;    // 32 k-slices
@@ -132,7 +135,7 @@ struct LagCfg {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kLagThreads) void corr_long_kernel(int K, int N,
+__global__ __launch_bounds__(kLagThreads) void corr_long_kernel(int K, int N, long long s_stride,
                                                                 const T* __restrict__ s,
                                                                 const T* __restrict__ r,
                                                                 T* __restrict__ g) {
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kLagThreads) void corr_long_kernel(int K, int N,
   T* sr = buf + CH;  // [CH + kLagBlock + 8] r chunk
   const int pair = blockIdx.y;
   const int R = K + N - 1;
-  const T* S = s + (long long)pair * N;
+  const T* S = s + (long long)pair * s_stride;
   const T* Rr = r + (long long)pair * R;
   const int n0 = blockIdx.x * kLagBlock;
   const int lg = threadIdx.x % kLagGroups;
@@ -187,12 +190,12 @@ __global__ __launch_bounds__(kLagThreads) void corr_long_kernel(int K, int N,
 }
 
 template <typename T>
-static hipError_t launch_conv_t(int batch, int K, int N, const void* h, const void* s,
-                                const void* x_obs, void* resid, void* grad_h, void* grad_s,
-                                hipStream_t st) {
+static hipError_t launch_conv_t(int batch, int K, int N, long long s_stride, const void* h,
+                                const void* s, const void* x_obs, void* resid, void* grad_h,
+                                void* grad_s, hipStream_t st) {
   const int R = K + N - 1;
   hipLaunchKernelGGL(conv_full_kernel<T>, dim3((R + kConvTile - 1) / kConvTile, batch),
-                     dim3(kConvThreads), 0, st, K, N, R, static_cast<const T*>(h),
+                     dim3(kConvThreads), 0, st, K, N, R, s_stride, static_cast<const T*>(h),
                      static_cast<const T*>(s), static_cast<const T*>(x_obs),
                      static_cast<T*>(resid));
   hipError_t e = hipGetLastError();
@@ -206,7 +209,7 @@ static hipError_t launch_conv_t(int batch, int K, int N, const void* h, const vo
   }
   if (grad_h) {
     hipLaunchKernelGGL(corr_long_kernel<T>, dim3((K + kLagBlock - 1) / kLagBlock, batch),
-                       dim3(kLagThreads), 0, st, K, N, static_cast<const T*>(s),
+                       dim3(kLagThreads), 0, st, K, N, s_stride, static_cast<const T*>(s),
                        static_cast<const T*>(resid), static_cast<T*>(grad_h));
     e = hipGetLastError();
   }
@@ -215,9 +218,10 @@ static hipError_t launch_conv_t(int batch, int K, int N, const void* h, const vo
 
 hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, const void* s,
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
-                            hipStream_t st) {
-  return dtype ? launch_conv_t<double>(batch, K, N, h, s, x_obs, resid, grad_h, grad_s, st)
-               : launch_conv_t<float>(batch, K, N, h, s, x_obs, resid, grad_h, grad_s, st);
+                            hipStream_t st, bool shared_s) {
+  const long long ss = shared_s ? 0 : N;
+  return dtype ? launch_conv_t<double>(batch, K, N, ss, h, s, x_obs, resid, grad_h, grad_s, st)
+               : launch_conv_t<float>(batch, K, N, ss, h, s, x_obs, resid, grad_h, grad_s, st);
 }
 
 }  // namespace aw

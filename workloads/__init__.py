@@ -17,6 +17,13 @@ available):
   gu, gv ~ U[-0.25, 0.25]; clipped to [0,1].
 * ``gen_noise``: i.i.d. N(0, sigma^2), sigma = 1e-3 by default.
 * ``gen_conv_pair``: h ~ N(0,1) of length K, s ~ N(0,1) of length N.
+* ``gen_blind_problem``: multi-channel blind estimation (stand-in for the
+  simulated underwater acoustic data): an impulsive source of length N (a few
+  impulses of N(0,1) amplitude at sorted random positions), C sparse multipath
+  channels of length K (arrivals at random delays, amplitudes N(0,1) decaying
+  with delay, each followed by a short geometric tail), N(0, sigma^2) noise
+  for each channel output (length K+N-1), and N(0,1) starting guesses of the
+  estimated lengths K_est, N_est (K_est + N_est = K + N).
 * ``gen_batched_config``: the uneven batch (image sides drawn from
   {512, 768, ..., 4096} independently per axis, levels from {3,4,5}, filters
   from {Haar, Daubechies-4, Daubechies-8}, PSF sigma ~ U[1,4], radius
@@ -102,3 +109,28 @@ def gen_cnn_init(rng: np.random.Generator, layers, out_scale: float = 0.1) -> np
         parts.append(w)
         parts.append(np.zeros(co))
     return np.concatenate(parts)
+
+
+def gen_blind_problem(rng: np.random.Generator, C: int = 2, K: int = 894, N: int = 1717,
+                      K_est: int | None = None, N_est: int | None = None,
+                      sigma: float = 0.005, n_arrivals: int = 6, n_impulses: int = 5):
+    """(h_true [C, K], s_true [N], noise [C, K+N-1], h0 [C, K_est], s0 [N_est])."""
+    K_est = K if K_est is None else K_est
+    N_est = N if N_est is None else N_est
+    if K_est + N_est != K + N:
+        raise ValueError("K_est + N_est must equal K + N (observed length K+N-1)")
+    s = np.zeros(N)
+    pos = np.sort(rng.choice(N, n_impulses, replace=False))
+    s[pos] = rng.standard_normal(n_impulses)
+    h = np.zeros((C, K))
+    for c in range(C):
+        delays = np.sort(rng.choice(K, n_arrivals, replace=False))
+        for d in delays:
+            amp = rng.standard_normal() * math.exp(-2.0 * d / K)
+            for t in range(8):
+                if d + t < K:
+                    h[c, d + t] += amp * 0.6 ** t
+    noise = sigma * rng.standard_normal((C, K + N - 1))
+    h0 = rng.standard_normal((C, K_est))
+    s0 = rng.standard_normal(N_est)
+    return h, s, noise, h0, s0
