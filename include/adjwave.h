@@ -168,6 +168,27 @@ aw_status blur(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* x, v
 aw_status blur_adjoint(const aw_blur* b, aw_dtype dtype, int32_t batch, const void* y,
                        void* x, void* stream);
 
+/* y = R x by DCT-II diagonalisation (Sec. "Example 1": for reflexive
+ * boundaries R can be applied in O(N log N); pays off over the direct
+ * kernels for wide PSFs). With half-point reflexive boundaries (repeating with
+ * period 2N) and a symmetric PSF g of any radius, each axis of R is
+ * C^{-1} diag(lambda) C with C the DCT-II and lambda_k = g_0 + 2 sum_{u>=1}
+ * g_u cos(pi k u / N); then R^* = R. The plan holds the eigenvalues of both
+ * axes (device memory, freed by destroy). rows and cols: powers of two in
+ * [2, 4096]; taps: host array of 2*radius+1 doubles, symmetric to 1e-14
+ * relative (else AW_EUNSUPPORTED), 0 <= radius <= 16384. */
+typedef struct aw_blur_dct aw_blur_dct;
+aw_status aw_blur_dct_create(int32_t rows, int32_t cols, int32_t radius, const double* taps,
+                             aw_dtype dtype, aw_blur_dct** plan);
+aw_status aw_blur_dct_destroy(aw_blur_dct* plan);
+/* Workspace of aw_blur_dct_apply: two images per batch entry. */
+aw_status aw_blur_dct_workspace(const aw_blur_dct* plan, int32_t batch, size_t* bytes);
+/* y = R x for batch images [batch][rows][cols] in the plan's dtype (x may
+ * alias y): five passes (row transform, transpose, column transform with the
+ * eigenvalue scaling and inverse, transpose, row inverse). */
+aw_status aw_blur_dct_apply(const aw_blur_dct* plan, int32_t batch, const void* x, void* y,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------- composed operators */
 
 /* img = A coef = R W coef (eq. 1). w and b must describe the same image size. */

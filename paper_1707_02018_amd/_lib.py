@@ -64,6 +64,10 @@ SIGNATURES = {
                    _P],
     "aw_objective": [_W, _B, _i32, _i32, _P, _dbl, _P, _P, _P, _sz, _P],
     "conv_adjoint_pair": [_i32, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _P],
+    "aw_blur_dct_create": [_i32, _i32, _i32, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(_P)],
+    "aw_blur_dct_destroy": [_P],
+    "aw_blur_dct_workspace": [_P, _i32, ctypes.POINTER(_sz)],
+    "aw_blur_dct_apply": [_P, _i32, _P, _P, _P, _sz, _P],
     "aw_conv_multichannel": [_i32, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "aw_huber_tv": [_i32, _i32, _i32, _P, _dbl, _dbl, _P, _P, _P],
     "aw_prox_l1": [_i32, _i64, _P, _P, _dbl, _dbl, _P, _P, _P],

@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libadjwave.so")
 SOURCES = ["api.hip", "wavelet.hip", "blur.hip", "fista.hip", "conv.hip", "batch.hip", "cnn.hip",
-           "fused.hip", "blind.hip"]
+           "fused.hip", "blind.hip", "dct.hip"]
 HEADERS = ["aw_internal.hpp", os.path.join("..", "..", "include", "adjwave.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -805,6 +805,104 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
   return st == AW_OK ? ok() : st;
 }
 
+// ------------------------------------------------------ R via the DCT-II
+struct aw_blur_dct {
+  int rows = 0, cols = 0, radius = 0;
+  aw_dtype dtype = AW_F32;
+  void* lam = nullptr;  // eigenvalues: rows values (rows axis), then cols values
+};
+
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+aw_status aw_blur_dct_create(int32_t rows, int32_t cols, int32_t radius, const double* taps,
+                             aw_dtype dtype, aw_blur_dct** plan) {
+  aw_status st;
+  if (!plan) return fail(AW_EINVAL, "plan pointer is NULL");
+  *plan = nullptr;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if (!pow2_in(rows, 2, 4096) || !pow2_in(cols, 2, 4096))
+    return fail(AW_EUNSUPPORTED, "DCT blur needs power-of-two sizes in [2, 4096] (%dx%d)", rows,
+                cols);
+  if (radius < 0 || radius > 16384) return fail(AW_EINVAL, "radius=%d outside [0, 16384]", radius);
+  if (!taps) return fail(AW_EINVAL, "taps is NULL");
+  double mag = 0.0;
+  for (int i = 0; i < 2 * radius + 1; ++i) {
+    if (!std::isfinite(taps[i])) return fail(AW_EINVAL, "PSF tap %d is not finite", i);
+    mag += std::fabs(taps[i]);
+  }
+  for (int u = 1; u <= radius; ++u)
+    if (std::fabs(taps[radius + u] - taps[radius - u]) > 1e-14 * mag)
+      return fail(AW_EUNSUPPORTED, "the DCT-II diagonalises R only for a symmetric PSF");
+  const size_t need = aw::blur_dct_lds(dtype == AW_F64, std::max(rows, cols));
+  if (need > 160 * 1024) return fail(AW_EUNSUPPORTED, "row of %zu bytes exceeds LDS", need);
+  // lambda_k = g_0 + 2 sum_u g_u cos(pi k u / N) along each axis
+  std::vector<double> lam((size_t)rows + cols);
+  for (int axis = 0; axis < 2; ++axis) {
+    const int N = axis ? cols : rows;
+    double* L = lam.data() + (axis ? rows : 0);
+    for (int k = 0; k < N; ++k) {
+      double v = taps[radius];
+      for (int u = 1; u <= radius; ++u) v += 2.0 * taps[radius + u] * std::cos(M_PI * k * u / N);
+      L[k] = v;
+    }
+  }
+  aw_blur_dct* p = new aw_blur_dct;
+  p->rows = rows;
+  p->cols = cols;
+  p->radius = radius;
+  p->dtype = dtype;
+  const size_t n = lam.size();
+  if (hipMalloc(&p->lam, n * dsize(dtype)) != hipSuccess) {
+    delete p;
+    return fail(AW_EHIP, "eigenvalue table allocation failed");
+  }
+  hipError_t e;
+  if (dtype == AW_F64) {
+    e = hipMemcpy(p->lam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> lf(lam.begin(), lam.end());
+    e = hipMemcpy(p->lam, lf.data(), n * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    (void)hipFree(p->lam);
+    delete p;
+    return hip_check(e, "eigenvalue upload");
+  }
+  *plan = p;
+  return ok();
+}
+
+aw_status aw_blur_dct_destroy(aw_blur_dct* plan) {
+  if (!plan) return ok();
+  const hipError_t e = hipFree(plan->lam);
+  delete plan;
+  return e == hipSuccess ? ok() : hip_check(e, "plan free");
+}
+
+aw_status aw_blur_dct_workspace(const aw_blur_dct* plan, int32_t batch, size_t* bytes) {
+  if (!plan || !bytes) return fail(AW_EINVAL, "NULL argument");
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  *bytes = 2 * align_up((size_t)batch * plan->rows * plan->cols * dsize(plan->dtype));
+  return ok();
+}
+
+aw_status aw_blur_dct_apply(const aw_blur_dct* plan, int32_t batch, const void* x, void* y,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  size_t need = 0;
+  aw_status st = aw_blur_dct_workspace(plan, batch, &need);
+  if (st != AW_OK) return st;
+  if (!x || !y) return fail(AW_EINVAL, "NULL data pointer");
+  if ((st = need_ws(workspace, workspace_bytes, need)) != AW_OK) return st;
+  const size_t half = need / 2;
+  const int di = plan->dtype == AW_F64;
+  const char* lam = static_cast<const char*>(plan->lam);
+  st = hip_check(aw::launch_blur_dct(di, plan->rows, plan->cols, batch, lam,
+                                     lam + plan->rows * dsize(plan->dtype), x, y, workspace,
+                                     wsp(workspace, half), (hipStream_t)stream),
+                 "DCT blur launch");
+  return st == AW_OK ? ok() : st;
+}
+
 aw_status aw_conv_multichannel(aw_dtype dtype, int32_t channels, int32_t K, int32_t N,
                                const void* h, const void* s, const void* x_obs, void* resid,
                                void* grad_h, void* grad_s_parts, void* grad_s, double* rnorm,

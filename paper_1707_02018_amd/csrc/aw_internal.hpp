@@ -371,6 +371,14 @@ hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, c
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
                             hipStream_t st, bool shared_s = false);
 
+// R by DCT-II diagonalisation (dct.hip): lam_r / lam_c are the eigenvalues
+// along the rows axis (length rows) and the columns axis (length cols); w1, w2
+// hold batch * rows * cols values each; x may alias y.
+size_t blur_dct_lds(int dtype, int n);
+hipError_t launch_blur_dct(int dtype, int rows, int cols, int batch, const void* lam_r,
+                           const void* lam_c, const void* x, void* y, void* w1, void* w2,
+                           hipStream_t s);
+
 // Multi-channel blind channel estimation helpers (blind.hip).
 hipError_t launch_sum_rows(int dtype, int rows, long long n, const void* in, void* out,
                            hipStream_t s);

@@ -245,6 +245,44 @@ def blur_adjoint(b: BlurSpec, y: torch.Tensor, out=None) -> torch.Tensor:
     return _blur_call("blur_adjoint", b, y, out)
 
 
+class BlurDCT:
+    """R by DCT-II diagonalisation: a symmetric PSF of any radius (taps, host
+    float64 array of odd length), power-of-two sizes up to 4096."""
+
+    def __init__(self, rows: int, cols: int, taps, dtype=torch.float32):
+        taps = np.ascontiguousarray(np.asarray(taps, dtype=np.float64))
+        if taps.ndim != 1 or len(taps) % 2 == 0:
+            raise ValueError("taps: odd-length 1-D array")
+        self.rows, self.cols, self.dtype = rows, cols, dtype
+        self.radius = (len(taps) - 1) // 2
+        self._plan = ctypes.c_void_p()
+        code = _lib.F64 if dtype == torch.float64 else _lib.F32
+        check("aw_blur_dct_create", load().aw_blur_dct_create(
+            rows, cols, self.radius, taps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), code,
+            ctypes.byref(self._plan)))
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            load().aw_blur_dct_destroy(plan)
+            self._plan = None
+
+    def apply(self, x: torch.Tensor, out=None) -> torch.Tensor:
+        _dev(x)
+        if x.dtype != self.dtype:
+            raise TypeError(f"{self.dtype} tensors expected")
+        batch = _batch_img(x, self.rows, self.cols)
+        if out is None:
+            out = torch.empty_like(x)
+        n = ctypes.c_size_t()
+        check("aw_blur_dct_workspace", load().aw_blur_dct_workspace(self._plan, batch,
+                                                                    ctypes.byref(n)))
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=x.device)
+        check("aw_blur_dct_apply", load().aw_blur_dct_apply(
+            self._plan, batch, _ptr(x), _ptr(_dev(out)), _ptr(ws), n.value, _stream(x)))
+        return out
+
+
 # -------------------------------------------------------------- A, A^*
 def apply_A(w: WaveletSpec, b: BlurSpec, coef: torch.Tensor, out=None) -> torch.Tensor:
     _dev(coef)

@@ -233,3 +233,22 @@ def test_biorthogonal_layout_and_validation(lib, bc, mode):
     bad = ref_s.copy()
     bad[4] += 1e-6
     assert _einval(lib, _bior(hs=bad))
+
+
+def test_blur_dct_plan_validates_before_device_work(lib):
+    """Invalid DCT-blur plans are refused on the host (no device memory)."""
+    g = obl.gaussian_taps(2.0, 4)
+    arr = (ctypes.c_double * len(g))(*g)
+    plan = ctypes.c_void_p()
+    assert lib.aw_blur_dct_create(48, 64, 4, arr, 0, ctypes.byref(plan)) == _lib.EUNSUPPORTED
+    assert lib.aw_blur_dct_create(64, 8192, 4, arr, 0, ctypes.byref(plan)) == _lib.EUNSUPPORTED
+    asym = g.copy()
+    asym[0] += 1e-3
+    arr2 = (ctypes.c_double * len(asym))(*asym)
+    assert lib.aw_blur_dct_create(64, 64, 4, arr2, 0, ctypes.byref(plan)) == _lib.EUNSUPPORTED
+    assert lib.aw_blur_dct_create(64, 64, -1, arr, 0, ctypes.byref(plan)) == _lib.EINVAL
+    assert lib.aw_blur_dct_create(64, 64, 4, None, 0, ctypes.byref(plan)) == _lib.EINVAL
+    assert lib.aw_blur_dct_create(64, 64, 4, arr, 7, ctypes.byref(plan)) == _lib.EINVAL
+    assert lib.aw_blur_dct_create(64, 64, 4, arr, 0, None) == _lib.EINVAL
+    assert plan.value is None
+    assert lib.aw_blur_dct_destroy(None) == _lib.OK

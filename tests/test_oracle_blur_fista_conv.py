@@ -38,6 +38,20 @@ def test_blur_symmetric_psf(sigma, r, N):
     np.testing.assert_allclose(D, np.diag(lam), atol=1e-13)
 
 
+@pytest.mark.parametrize("N,r", [(16, 40), (8, 30), (5, 17), (32, 100)])
+def test_blur_dct_diagonalisation_any_radius(N, r):
+    """The reflexive extension repeats with period 2N, so the DCT-II still
+    diagonalises R when the PSF is wider than the signal (several
+    reflections), with the same closed-form eigenvalues: the basis of the DCT
+    route for wide PSFs."""
+    g = bl.gaussian_taps(0.4 * r, r)
+    Rm = blur_matrix_1d(N, g)
+    C = scipy.fft.dct(np.eye(N), type=2, norm="ortho", axis=0)
+    k = np.arange(N)
+    lam = g[r] + 2.0 * sum(g[r + u] * np.cos(np.pi * k * u / N) for u in range(1, r + 1))
+    np.testing.assert_allclose(C @ Rm @ C.T, np.diag(lam), atol=1e-13)
+
+
 @pytest.mark.parametrize("N,r", [(7, 3), (12, 5), (3, 4), (20, 12)])
 def test_blur_adjoint_is_transpose_any_psf(N, r):
     """Structural R^* (correlate, fold halo) equals R^T, also for a
