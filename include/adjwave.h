@@ -117,7 +117,8 @@ aw_status aw_daubechies(int32_t taps, double* lo_out);
 aw_status aw_cdf97(double* lo_syn_out, double* lo_ana_out);
 
 /* Normalised Gaussian PSF taps g[u] ~ exp(-u^2/(2 sigma^2)), |u| <= radius
- * (host computation; writes 2*radius+1 doubles). */
+ * (host computation; writes 2*radius+1 doubles; 0 <= radius <= 16384: the
+ * direct blur takes radius <= AW_MAX_RADIUS, the DCT route any of these). */
 aw_status aw_gaussian_psf(double sigma, int32_t radius, double* taps_out);
 
 /* Coefficient layout: ncoef per image and the per-level sizes along rows and

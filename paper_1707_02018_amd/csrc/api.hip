@@ -494,7 +494,7 @@ aw_status aw_cdf97(double* lo_syn_out, double* lo_ana_out) {
 
 aw_status aw_gaussian_psf(double sigma, int32_t radius, double* taps_out) {
   if (!taps_out) return fail(AW_EINVAL, "output pointer is NULL");
-  if (!(sigma > 0.0) || radius < 0 || radius > AW_MAX_RADIUS)
+  if (!(sigma > 0.0) || radius < 0 || radius > 16384)
     return fail(AW_EINVAL, "sigma=%g radius=%d", sigma, radius);
   double s = 0.0;
   for (int u = -radius; u <= radius; ++u) {

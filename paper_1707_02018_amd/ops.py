@@ -118,6 +118,9 @@ class BlurSpec:
             self.taps = gaussian_psf(self.sigma, self.radius)
         self.taps = np.asarray(self.taps, dtype=np.float64)
         self.radius = (len(self.taps) - 1) // 2
+        if len(self.taps) > 2 * _lib.MAX_RADIUS + 1:
+            raise ValueError(f"radius {self.radius} > {_lib.MAX_RADIUS}: the tile kernels take "
+                             "narrower PSFs (BlurDCT applies wider symmetric ones)")
         c = _lib.Blur()
         c.rows, c.cols, c.radius = self.rows, self.cols, self.radius
         for k, v in enumerate(self.taps):
