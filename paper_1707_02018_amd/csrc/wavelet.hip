@@ -131,10 +131,13 @@ hipError_t launch_synth_level(int dtype, int L, const double* lo, const SynthLev
 // bands that tile needs (halos recomputed) into LDS. Every value is computed
 // by the same arithmetic as the per-level kernels, so the result is bitwise
 // the same.
+// Output tile of a chain workgroup (a tile of a_1).
+constexpr int kChainTR = 32, kChainTC = 128;
+
 template <typename T, int L, int BC>
 __global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int TR = SynthTile<T>::TR, TC = SynthTile<T>::TC;
+  constexpr int TR = kChainTR, TC = kChainTC;
   const int img = blockIdx.z;
   // rows [ra[k], rb[k]) x columns [ca[k], cb[k]) of level d[k]'s output
   int ra[kChainMax], rb[kChainMax], ca[kChainMax], cb[kChainMax];
@@ -193,8 +196,8 @@ template <int L, int BC>
 static size_t chain_plan_t(SynthChain& c) {
   using T = float;
   int lr[kChainMax], nr[kChainMax], lc[kChainMax], nc[kChainMax];
-  chain_axis<L, BC>(c, true, SynthTile<T>::TR, lr, nr);
-  chain_axis<L, BC>(c, false, SynthTile<T>::TC, lc, nc);
+  chain_axis<L, BC>(c, true, kChainTR, lr, nr);
+  chain_axis<L, BC>(c, false, kChainTC, lc, nc);
   size_t scratch = 0;
   for (int k = 0; k < c.nl; ++k)
     scratch = std::max(scratch, sizeof(T) * (size_t)(4 * nr[k] * nc[k] + 2 * lr[k] * nc[k]));
@@ -235,8 +238,8 @@ template <int L, int BC>
 static hipError_t launch_chain_t(const double* lo, const SynthChain& c, size_t lds, int batch,
                                  hipStream_t s) {
   using T = float;
-  dim3 grid((c.d[0].c.N + SynthTile<T>::TC - 1) / SynthTile<T>::TC,
-            (c.d[0].r.N + SynthTile<T>::TR - 1) / SynthTile<T>::TR, batch);
+  dim3 grid((c.d[0].c.N + kChainTC - 1) / kChainTC, (c.d[0].r.N + kChainTR - 1) / kChainTR,
+            batch);
   hipLaunchKernelGGL((synth_chain_kernel<T, L, BC>), grid, dim3(512), lds, s, c,
                      make_taps<T>(lo, L));
   return hipGetLastError();
