@@ -1,6 +1,9 @@
 // C ABI (include/adjwave.h): validation, coefficient layout, workspace
 // carving, and the per-level launch sequences of W, W^*, W^dagger,
-// (W^dagger)^*, R, R^*, A, A^*, one FISTA iteration and the convolution pair.
+// (W^dagger)^* (orthogonal and biorthogonal filters), R, R^*, A, A^* (two
+// kernels or one pass over the finest level), one FISTA iteration, the
+// convolution pair and its multi-channel form with the Huber TV pieces, the
+// learned warm start's CNN, and the DCT-II route for R.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -64,11 +64,11 @@ __device__ void fft_lds(typename Cx<T>::V* a, int N, int logN, T sign) {
 }
 
 // MODE 0: out = C x; MODE 1: out = C^{-1} x; MODE 2: out = C^{-1} (s_row lam . C x)
-// with s_row = lam_row[row % rows_per_image]. One workgroup per row of N.
+// with s_row = lam_row[row % rows_per_image]. One workgroup per row of N; in
+// may equal out (a row is read whole into LDS before any of it is written).
 template <typename T, int MODE>
 __global__ __launch_bounds__(kDctThreads) void dct_rows_kernel(int N, int logN, int rows_img,
-                                                               const T* __restrict__ in,
-                                                               T* __restrict__ out,
+                                                               const T* in, T* out,
                                                                const T* __restrict__ lam,
                                                                const T* __restrict__ lam_row) {
   using V = typename Cx<T>::V;

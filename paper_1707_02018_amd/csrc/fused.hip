@@ -2,7 +2,7 @@
 // aw_apply_A_fused; FISTA uses the separate kernels, which measured faster).
 //
 // A workgroup owns a TR x TC tile of the output. It synthesises the finest
-// wavelet level (W's last step, eq. 2 applied to the level-1 subbands) over
+// wavelet level (W's last step, E^dagger Phi^* of the level-1 subbands) over
 // the rows and columns the tile's blur window reaches (tile + PSF radius,
 // clipped to the image), scattering every value straight into the reflected
 // LDS window the blur reads: an image position lands in each window slot
@@ -10,7 +10,7 @@
 // (column pass, row pass) and optionally subtracts b. The full-resolution
 // W x never reaches memory, which saves one image write and one image read.
 // The cost: the window's halo is synthesised by every tile that needs it,
-// and the LDS footprint halves the resident workgroups.
+// and the larger LDS footprint lowers the resident workgroups.
 //
 // The synthesised values and the blur arithmetic are those of the separate
 // kernels, so the result is bitwise identical to synthesis followed by blur.
