@@ -13,7 +13,8 @@
 // FFT of its even/odd reordering (v_n = x_{2n}, v_{N-1-n} = x_{2n+1}); the
 // inverse rebuilds the complex spectrum from y_k and y_{N-k}, untwiddles, runs
 // the inverse FFT and undoes the reordering. The FFT is iterative radix-2
-// (bit-reversed load, N / 2 butterflies per stage). Columns are transformed
+// (bit-reversed load, N / 2 butterflies per stage, twiddles from a table
+// built once per row in LDS). Columns are transformed
 // as rows of a tiled transpose. Passes over the image: row DCT, transpose,
 // column DCT + scale + inverse (one kernel), transpose, row inverse.
 #include <hip/hip_runtime.h>
@@ -42,9 +43,11 @@ __device__ inline int bitrev(int i, int logN) {
 }
 
 // In-place radix-2 FFT of a[0..N) held in bit-reversed order, natural order
-// out; sign -1 forward, +1 inverse (unnormalised).
+// out; sign -1 forward, +1 inverse (unnormalised). tw[j] = (cos, sin)(2 pi j / N),
+// j < N / 2; stage s takes exp(sign 2 pi i j / 2^s) = tw[j N / 2^s].
 template <typename T>
-__device__ void fft_lds(typename Cx<T>::V* a, int N, int logN, T sign) {
+__device__ void fft_lds(typename Cx<T>::V* a, const typename Cx<T>::V* tw, int N, int logN,
+                        T sign) {
   using V = typename Cx<T>::V;
   for (int s = 1; s <= logN; ++s) {
     const int half = 1 << (s - 1);
@@ -52,8 +55,8 @@ __device__ void fft_lds(typename Cx<T>::V* a, int N, int logN, T sign) {
     for (int b = threadIdx.x; b < N / 2; b += kDctThreads) {
       const int j = b & (half - 1);
       const int i0 = ((b >> (s - 1)) << s) + j, i1 = i0 + half;
-      T sn, cs;
-      Cx<T>::sincospi_(sign * T(j) / T(half), &sn, &cs);  // exp(sign 2 pi i j / 2^s)
+      const V t0 = tw[j << (logN - s)];
+      const T cs = t0.x, sn = sign * t0.y;
       const V u = a[i0], w = a[i1];
       const V t = {cs * w.x - sn * w.y, cs * w.y + sn * w.x};
       a[i0] = V{u.x + t.x, u.y + t.y};
@@ -74,8 +77,14 @@ __global__ __launch_bounds__(kDctThreads) void dct_rows_kernel(int N, int logN, 
   using V = typename Cx<T>::V;
   extern __shared__ __align__(16) unsigned char smem[];
   V* a = reinterpret_cast<V*>(smem);
-  T* yb = reinterpret_cast<T*>(smem + sizeof(V) * N);
+  V* tw = a + N;
+  T* yb = reinterpret_cast<T*>(tw + N / 2);
   const long long row = blockIdx.x;
+  for (int j = threadIdx.x; j < N / 2; j += kDctThreads) {
+    T sn, cs;
+    Cx<T>::sincospi_(T(2 * j) / T(N), &sn, &cs);
+    tw[j] = V{cs, sn};
+  }
   const T* X = in + row * N;
   T* Y = out + row * N;
   const T invN = T(1) / T(N);
@@ -85,7 +94,7 @@ __global__ __launch_bounds__(kDctThreads) void dct_rows_kernel(int N, int logN, 
       a[bitrev(n, logN)] = V{X[2 * n], T(0)};
       a[bitrev(N - 1 - n, logN)] = V{X[2 * n + 1], T(0)};
     }
-    fft_lds<T>(a, N, logN, T(-1));
+    fft_lds<T>(a, tw, N, logN, T(-1));
     const T sr = MODE == 2 ? lam_row[row % rows_img] : T(1);
     for (int k = threadIdx.x; k < N; k += kDctThreads) {
       T sn, cs;
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(kDctThreads) void dct_rows_kernel(int N, int logN, 
     Cx<T>::sincospi_(T(k) * T(0.5) * invN, &sn, &cs);
     a[bitrev(k, logN)] = V{wr * cs - wi * sn, wr * sn + wi * cs};
   }
-  fft_lds<T>(a, N, logN, T(1));
+  fft_lds<T>(a, tw, N, logN, T(1));
   for (int n = threadIdx.x; n < N / 2; n += kDctThreads) {
     Y[2 * n] = a[n].x * invN;
     Y[2 * n + 1] = a[N - 1 - n].x * invN;
@@ -137,8 +146,8 @@ __global__ __launch_bounds__(256) void transpose_kernel(int rows, int cols, cons
 }
 
 template <typename T>
-static size_t dct_lds(int N) {
-  return sizeof(typename Cx<T>::V) * (size_t)N + sizeof(T) * (size_t)N;
+static size_t dct_lds(int N) {  // a[N], tw[N / 2], yb[N]
+  return sizeof(typename Cx<T>::V) * (size_t)(N + N / 2) + sizeof(T) * (size_t)N;
 }
 
 template <typename T, int MODE>
@@ -148,7 +157,7 @@ static hipError_t launch_rows(int N, long long nrows, int rows_img, const T* in,
   while ((1 << logN) < N) ++logN;
   const size_t lds = dct_lds<T>(N);
   auto kern = dct_rows_kernel<T, MODE>;
-  if (lds > 64 * 1024) {
+  if (lds >= 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

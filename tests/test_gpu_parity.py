@@ -171,14 +171,16 @@ def _cfg1(dt_seed=0):
     return rows, cols, h, psf, b
 
 
-@pytest.mark.parametrize("gradient", ["adjoint", "pinv"])
+@pytest.mark.parametrize("mode,gradient", [("sym", "adjoint"), ("sym", "pinv"),
+                                           ("zpd", "adjoint"), ("per", "adjoint"),
+                                           ("per_ext", "adjoint"), ("per_ext", "pinv")])
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
-def test_fista_step_from_oracle_state(dt, gradient):
+def test_fista_step_from_oracle_state(dt, mode, gradient):
     """One FISTA iteration from an identical state (k = 5), with the true
-    adjoint W^* or with W^dagger in its place."""
-    print(f"[fista step] 256x256 {dt} gradient={gradient}", flush=True)
+    adjoint W^* or with W^dagger in its place, in each boundary mode."""
+    print(f"[fista step] 256x256 {dt} mode={mode} gradient={gradient}", flush=True)
     rows, cols, h, psf, b = _cfg1()
-    prob = ofi.Problem(rows, cols, h, "sym", 3, psf)
+    prob = ofi.Problem(rows, cols, h, mode, 3, psf)
     rng = rng_for(5, 0)
     x_prev = rng.standard_normal(prob.ncoef) * 1e-2
     y = rng.standard_normal(prob.ncoef) * 1e-2
@@ -188,11 +190,11 @@ def test_fista_step_from_oracle_state(dt, gradient):
         t = ofi.t_next(t)
     beta = (t - 1.0) / ofi.t_next(t)
     x_ref, y_ref = ofi.fista_step(prob, x_prev, y, b, beta, lam, gradient=gradient)
-    if gradient == "pinv":  # the two maps differ in the sym mode
+    if gradient == "pinv":  # the two maps differ where E folds (sym, per_ext)
         x_adj, _ = ofi.fista_step(prob, x_prev, y, b, beta, lam)
         assert rel(x_adj, x_ref) > 100 * TOL[dt]
     r_ref = prob.A(y) - b
-    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc="sym")
+    w = ops.WaveletSpec(rows, cols, 3, lo=h, bc=mode)
     bs = ops.BlurSpec(rows, cols, taps=psf)
     bt = dev(b, dt)
     st = ops.FistaState(w, bs, bt, x0=dev(x_prev, dt), gradient=gradient)
