@@ -195,9 +195,78 @@ __device__ __forceinline__ void synth_put(const SynthWin& w, int base,
   }
 }
 
-template <typename T, int L, int BC, typename W>
+template <typename T, int L, int BC, bool LANES, typename W>
 __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>& f,
                                              const SynthWin& w, unsigned char* smem_raw, W& wr);
+
+// Lane-mapped layout of the synthesis loops (512 threads = 8 waves): a wave
+// takes window rows (row pairs, output rows) wv, wv + 8, ... and its 64 lanes
+// the columns 0..63; columns from 64 on (at most kSynthTailC) go to threads
+// (t >> 3, 64 + (t & 7)). Every address is then a wave-uniform base plus the
+// lane, with no per-item index division.
+constexpr int kSynthTailC = 8;
+constexpr int kSynthMaxRows = 32;  // window rows staged by the lane-mapped loads
+
+__device__ __forceinline__ bool synth_lanes_ok(const SynthWin& w) {
+  return w.nkr <= kSynthMaxRows && w.nkc <= 64 + kSynthTailC && (w.c1 - w.c0 + 1) / 2 <= 64 &&
+         (w.r1 - w.r0 + 1) / 2 <= 64;
+}
+
+// Window item (i, j) (bands interleaved a, H, V, D), zero outside the bands.
+template <typename T, int L, int BC>
+__device__ __forceinline__ typename Vec<T>::V4 synth_fetch(const SynthLevel& d, const SynthWin& w,
+                                                           int i, int j,
+                                                           const LdsBand<T>* abuf) {
+  const int Kr = d.r.K, Kc = d.c.K;
+  const T* A = static_cast<const T*>(d.a) + (long long)w.img * d.stride_a;
+  const T* HVD = static_cast<const T*>(d.hvd) + (long long)w.img * d.stride_hvd;
+  const long long band = (long long)Kr * Kc;
+  typename Vec<T>::V4 q;
+  q.x = q.y = q.z = q.w = T(0);
+  int kr = w.kwr + i, kc = w.kwc + j;
+  bool ok;
+  if (BC == PER) {
+    kr = posmod(kr, Kr);
+    kc = posmod(kc, Kc);
+    ok = true;
+  } else {
+    ok = (kr >= 0) && (kr < Kr) && (kc >= 0) && (kc < Kc);
+  }
+  if (ok) {
+    const long long off = (long long)kr * Kc + kc;
+    q.x = abuf ? abuf->p[(kr - abuf->r0) * abuf->pitch + (kc - abuf->c0)] : A[off];
+    q.y = HVD[off];
+    q.z = HVD[band + off];
+    q.w = HVD[2 * band + off];
+  }
+  return q;
+}
+
+template <typename T, int L, int BC>
+__device__ __forceinline__ void synth_stage_lanes(const SynthLevel& d, const SynthWin& w,
+                                                  unsigned char* smem_raw,
+                                                  const LdsBand<T>* abuf) {
+  using V4 = typename Vec<T>::V4;
+  constexpr int RPW = kSynthMaxRows / 8;
+  V4* sc = reinterpret_cast<V4*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ti = threadIdx.x >> 3, tj = 64 + (threadIdx.x & 7);
+  const bool main_col = lane < w.nkc, tail = ti < w.nkr && tj < w.nkc;
+  V4 q[RPW], qt;
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int i = wv + 8 * k;
+    if (i < w.nkr && main_col) q[k] = synth_fetch<T, L, BC>(d, w, i, lane, abuf);
+  }
+  if (tail) qt = synth_fetch<T, L, BC>(d, w, ti, tj, abuf);
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int i = wv + 8 * k;
+    if (i < w.nkr && main_col) sc[i * w.nkc + lane] = q[k];
+  }
+  if (tail) sc[ti * w.nkc + tj] = qt;
+}
 
 // Synthesis of one level at the output rectangle [r0, r1) x [c0, c1)
 // (r0, c0 even) of image `img`; each output value goes to wr.one(row, col, v)
@@ -205,24 +274,31 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
 // the staged coefficient window (nkr x nkc x 4 values) followed by the
 // column-pass rows ((r1 - r0) x nkc x 2 values). With abuf, the approximation
 // band comes from LDS (it must cover the window's part inside the band).
-template <typename T, int L, int BC, typename W>
+// Needs 512 threads. LANES selects the lane-mapped loops where the window
+// fits them (the per-level tiles); otherwise items are spread over threads
+// (the chained levels' irregular rectangles, where that measured faster).
+template <typename T, int L, int BC, bool LANES = false, typename W>
 __device__ __forceinline__ void synth_rect(const SynthLevel& d, const Taps<T>& f, int r0, int r1,
                                            int c0, int c1, int img, unsigned char* smem_raw,
                                            W& wr, const LdsBand<T>* abuf = nullptr) {
   const SynthWin w = synth_win<L, BC>(d, r0, r1, c0, c1, img);
-  // 1. stage the coefficient window; each thread issues a batch of loads
-  //    before writing LDS
-  for (int base = 0; base < w.nkr * w.nkc; base += 512 * kSynthCH) {
-    typename Vec<T>::V4 q[kSynthCH];
-    synth_load<T, L, BC>(d, w, base, q, abuf);
-    synth_put<T>(w, base, q, smem_raw);
+  // 1. stage the coefficient window; each thread issues its loads before
+  //    writing LDS
+  if (LANES && synth_lanes_ok(w)) {
+    synth_stage_lanes<T, L, BC>(d, w, smem_raw, abuf);
+  } else {
+    for (int base = 0; base < w.nkr * w.nkc; base += 512 * kSynthCH) {
+      typename Vec<T>::V4 q[kSynthCH];
+      synth_load<T, L, BC>(d, w, base, q, abuf);
+      synth_put<T>(w, base, q, smem_raw);
+    }
   }
   __syncthreads();
-  synth_passes<T, L, BC>(d, f, w, smem_raw, wr);
+  synth_passes<T, L, BC, LANES>(d, f, w, smem_raw, wr);
 }
 
 // Column then row passes over the staged window (steps 2 and 3).
-template <typename T, int L, int BC, typename W>
+template <typename T, int L, int BC, bool LANES, typename W>
 __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>& f,
                                              const SynthWin& w, unsigned char* smem_raw, W& wr) {
   constexpr int HL = L / 2;
@@ -244,9 +320,7 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
   //    last row run a separate pass, so no wave mixes the two.
   int sL, sR, nsp;
   special_range(r0, r1, Nr, er, SHIFT, sL, sR, nsp);
-  for (int item = threadIdx.x; item < (sR - sL) * nkc; item += blockDim.x) {
-    const int s = sL + item / nkc;
-    const int j = item - (item / nkc) * nkc;
+  auto col_pair = [&](int s, int j) {
     const int p0 = r0 + 2 * s;
     T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
     const int k1 = synth_k0(p0 + er, L, BC) - kwr;
@@ -286,6 +360,20 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
     v1.y = hi1;
     st[(2 * s) * nkc + j] = v0;
     st[(2 * s + 1) * nkc + j] = v1;
+  };
+  const bool lanes = LANES && synth_lanes_ok(w);
+  if (lanes) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane < nkc)
+      for (int s = sL + wv; s < sR; s += 8) col_pair(s, lane);
+    const int s = sL + (threadIdx.x >> 3), j = 64 + (threadIdx.x & 7);
+    if (s < sR && j < nkc) col_pair(s, j);
+  } else {
+    for (int item = threadIdx.x; item < (sR - sL) * nkc; item += blockDim.x) {
+      const int s = sL + item / nkc;
+      col_pair(s, item - (item / nkc) * nkc);
+    }
   }
   // border rows: p + e and, near an edge, the reflected preimage
   // (e - 1 - p on the left, 2N - 1 - p + e on the right), weighted 1/mult
@@ -322,10 +410,7 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
   special_range(c0, c1, Nc, ec, SHIFT, qL, qR, nsc);
   const int QC = (c1 - c0 + 1) / 2;
   const int nrows = r1 - r0;
-  for (int item = threadIdx.x; item < nrows * QC; item += blockDim.x) {
-    const int pr = item / QC;
-    const int q = item - pr * QC;
-    if (q < qL || q >= qR) continue;
+  auto row_pair = [&](int pr, int q) {
     const int p = c0 + 2 * q;
     const V2* row = st + pr * nkc;
     T o0 = T(0), o1 = T(0);
@@ -352,6 +437,18 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
       }
     }
     wr.pair(r0 + pr, p, o0, o1);
+  };
+  if (lanes) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane >= qL && lane < qR)
+      for (int pr = wv; pr < nrows; pr += 8) row_pair(pr, lane);
+  } else {
+    for (int item = threadIdx.x; item < nrows * QC; item += blockDim.x) {
+      const int pr = item / QC;
+      const int q = item - pr * QC;
+      if (q >= qL && q < qR) row_pair(pr, q);
+    }
   }
   for (int item = threadIdx.x; item < nrows * nsc; item += blockDim.x) {
     const int pr = item / nsc;
@@ -370,6 +467,186 @@ __device__ __forceinline__ void synth_passes(const SynthLevel& d, const Taps<T>&
     }
     if (d.pinv && cnt > 1) acc *= cnt == 2 ? T(0.5) : T(1) / T(cnt);
     wr.one(r0 + pr, p, acc);
+  }
+}
+
+// ------------------------------------------------ interior synthesis tiles
+// An FP32 tile of 128 output columns whose outputs are all regular (a full
+// tile, no border row or column, the coefficient window inside the bands)
+// runs with a fixed thread layout: one wave per window row, row pair or
+// output row and the 64 lanes along the columns, so every LDS and global
+// address is a wave-uniform base plus the lane (no per-item index division).
+// The taps and their order are those of synth_passes: the values are bitwise
+// the same.
+template <int L, int BC, int TR>
+struct FastSynth {
+  static constexpr int HL = L / 2;
+  static constexpr bool SHIFT = (BC == SYM);
+  static constexpr int NKR = TR / 2 + HL - (SHIFT ? 0 : 1);  // window rows
+  static constexpr int NKC = 64 + HL - (SHIFT ? 0 : 1);      // window columns
+  static constexpr int TAILC = NKC - 64;                     // columns past the lanes
+};
+
+template <int L, int BC, int TR, int TC>
+__device__ __forceinline__ bool synth_fast_ok(const SynthLevel& d, const SynthWin& w,
+                                              const void* out) {
+  using G = FastSynth<L, BC, TR>;
+  if constexpr (TC != 128 || (BC != SYM && BC != ZPD && BC != PER)) {
+    return false;
+  } else {
+    if (w.r1 - w.r0 != TR || w.c1 - w.c0 != TC) return false;
+    if (BC == SYM && (w.r0 < d.r.e || w.r1 > d.r.N - d.r.e || w.c0 < d.c.e ||
+                      w.c1 > d.c.N - d.c.e))
+      return false;
+    if (w.nkr != G::NKR || w.nkc != G::NKC) return false;
+    if (w.kwr < 0 || w.kwr + G::NKR > d.r.K || w.kwc < 0 || w.kwc + G::NKC > d.c.K) return false;
+    if ((long long)d.r.K * d.c.K >= (1LL << 31)) return false;  // 32-bit offsets in a band
+    return (d.c.N & 1) == 0 && (reinterpret_cast<uintptr_t>(out) & 7) == 0;
+  }
+}
+
+// Column-direction synthesis of row pair s at window column j (FP32), into
+// rows 2s and 2s + 1 of the column-pass output.
+template <int L, int BC, int TR>
+__device__ __forceinline__ void fast_col_pair(const float4* sc, float2* st, const Taps<float>& f,
+                                              int s, int j) {
+  using G = FastSynth<L, BC, TR>;
+  constexpr int HL = G::HL, NKC = G::NKC;
+  float lo0 = 0.f, hi0 = 0.f, lo1 = 0.f, hi1 = 0.f;
+  if constexpr (G::SHIFT) {  // row 2s: odd taps; row 2s + 1: even taps one row down
+    float4 q[HL + 1];
+#pragma unroll
+    for (int m = 0; m <= HL; ++m) q[m] = sc[(s + HL - m) * NKC + j];
+#pragma unroll
+    for (int m = 0; m < HL; ++m) {
+      lo0 += q[m + 1].x * f.h[2 * m + 1];
+      lo0 += q[m + 1].y * f.g[2 * m + 1];
+      hi0 += q[m + 1].z * f.h[2 * m + 1];
+      hi0 += q[m + 1].w * f.g[2 * m + 1];
+      lo1 += q[m].x * f.h[2 * m];
+      lo1 += q[m].y * f.g[2 * m];
+      hi1 += q[m].z * f.h[2 * m];
+      hi1 += q[m].w * f.g[2 * m];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < HL; ++m) {
+      const float4 q = sc[(s + HL - 1 - m) * NKC + j];
+      lo0 += q.x * f.h[2 * m];
+      lo0 += q.y * f.g[2 * m];
+      hi0 += q.z * f.h[2 * m];
+      hi0 += q.w * f.g[2 * m];
+      lo1 += q.x * f.h[2 * m + 1];
+      lo1 += q.y * f.g[2 * m + 1];
+      hi1 += q.z * f.h[2 * m + 1];
+      hi1 += q.w * f.g[2 * m + 1];
+    }
+  }
+  st[(2 * s) * NKC + j] = make_float2(lo0, hi0);
+  st[(2 * s + 1) * NKC + j] = make_float2(lo1, hi1);
+}
+
+// With LDSA the approximation band is read from abuf (LDS) instead of d.a.
+template <int L, int BC, int TR, bool LDSA = false>
+__device__ __forceinline__ void synth_tile_fast(const SynthLevel& d, const Taps<float>& f,
+                                                const SynthWin& w, unsigned char* smem_raw,
+                                                const LdsBand<float>* abuf = nullptr) {
+  using G = FastSynth<L, BC, TR>;
+  constexpr int HL = G::HL, NKR = G::NKR, NKC = G::NKC, TAILC = G::TAILC, NWAVE = 8;
+  float4* sc = reinterpret_cast<float4*>(smem_raw);        // [NKR][NKC] (a, H, V, D)
+  float2* st = reinterpret_cast<float2*>(sc + NKR * NKC);  // [TR][NKC] (lo, hi)
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int Kc = d.c.K;
+  const long long band = (long long)d.r.K * Kc;
+  const float* A = static_cast<const float*>(d.a) + (long long)w.img * d.stride_a;
+  const float* H = static_cast<const float*>(d.hvd) + (long long)w.img * d.stride_hvd;
+  const float* V = H + band;
+  const float* D = V + band;
+  const int base = w.kwr * Kc + w.kwc;
+
+  // 1. window: wave wv loads rows wv, wv + 8, ... at lanes 0..63; the
+  //    TAILC columns from 64 on go to threads 0 .. NKR * TAILC - 1. Every load
+  //    of a thread is issued before its LDS writes.
+  constexpr int RPW = (NKR + NWAVE - 1) / NWAVE;
+  constexpr int TAILN = NKR * TAILC;
+  float4 q[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int i = wv + NWAVE * k;
+    if (i < NKR) {
+      const int o = base + i * Kc;
+      float a;
+      if constexpr (LDSA)
+        a = abuf->p[(w.kwr + i - abuf->r0) * abuf->pitch + (w.kwc + lane - abuf->c0)];
+      else
+        a = A[o + lane];
+      q[k] = make_float4(a, H[o + lane], V[o + lane], D[o + lane]);
+    }
+  }
+  float4 qt = make_float4(0.f, 0.f, 0.f, 0.f);
+  int ti = 0, tj = 0;
+  if constexpr (TAILN > 0) {
+    if ((int)threadIdx.x < TAILN) {
+      ti = threadIdx.x / TAILC;
+      tj = 64 + (threadIdx.x - ti * TAILC);
+      const int o = base + ti * Kc + tj;
+      float a;
+      if constexpr (LDSA)
+        a = abuf->p[(w.kwr + ti - abuf->r0) * abuf->pitch + (w.kwc + tj - abuf->c0)];
+      else
+        a = A[o];
+      qt = make_float4(a, H[o], V[o], D[o]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int i = wv + NWAVE * k;
+    if (i < NKR) sc[i * NKC + lane] = q[k];
+  }
+  if constexpr (TAILN > 0) {
+    if ((int)threadIdx.x < TAILN) sc[ti * NKC + tj] = qt;
+  }
+  __syncthreads();
+
+  // 2. columns: wave wv takes row pairs wv, wv + 8, ...; the pairs' tail
+  //    columns go to threads 0 .. TR / 2 * TAILC - 1
+  for (int s = wv; s < TR / 2; s += NWAVE) fast_col_pair<L, BC, TR>(sc, st, f, s, lane);
+  if constexpr (TAILC > 0) {
+    for (int item = threadIdx.x; item < TR / 2 * TAILC; item += 512) {
+      const int s = item / TAILC;
+      fast_col_pair<L, BC, TR>(sc, st, f, s, 64 + (item - s * TAILC));
+    }
+  }
+  __syncthreads();
+
+  // 3. rows: wave wv takes output rows wv, wv + 8, ...; lane = output pair
+  float* O = static_cast<float*>(d.out) + (long long)w.img * d.stride_out + w.c0 + 2 * lane;
+  for (int pr = wv; pr < TR; pr += NWAVE) {
+    const float2* row = st + pr * NKC + lane;
+    float o0 = 0.f, o1 = 0.f;
+    if constexpr (G::SHIFT) {
+      float2 v[HL + 1];
+#pragma unroll
+      for (int m = 0; m <= HL; ++m) v[m] = row[HL - m];
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        o0 += v[m + 1].x * f.h[2 * m + 1];
+        o0 += v[m + 1].y * f.g[2 * m + 1];
+        o1 += v[m].x * f.h[2 * m];
+        o1 += v[m].y * f.g[2 * m];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < HL; ++m) {
+        const float2 v = row[HL - 1 - m];
+        o0 += v.x * f.h[2 * m];
+        o0 += v.y * f.g[2 * m];
+        o1 += v.x * f.h[2 * m + 1];
+        o1 += v.y * f.g[2 * m + 1];
+      }
+    }
+    *reinterpret_cast<float2*>(O + (long long)(w.r0 + pr) * d.c.N) = make_float2(o0, o1);
   }
 }
 

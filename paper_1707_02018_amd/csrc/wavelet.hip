@@ -28,16 +28,25 @@ __device__ __forceinline__ void synth_tile(const SynthLevel& d, const Taps<T>& f
   constexpr int TR = SynthTile<T, V>::TR, TC = SynthTile<T, V>::TC;
   const int r0 = by * TR, r1 = min(r0 + TR, d.r.N);
   const int c0 = bx * TC, c1 = min(c0 + TC, d.c.N);
+  if constexpr (sizeof(T) == 4) {
+    const SynthWin w = synth_win<L, BC>(d, r0, r1, c0, c1, img);
+    if (synth_fast_ok<L, BC, TR, TC>(d, w, static_cast<T*>(d.out) + (long long)img * d.stride_out)) {
+      synth_tile_fast<L, BC, TR>(d, f, w, smem_raw);
+      return;
+    }
+  }
   PlaneWriter<T> wr(static_cast<T*>(d.out) + (long long)img * d.stride_out, d.c.N);
-  synth_rect<T, L, BC>(d, f, r0, r1, c0, c1, img, smem_raw, wr);
+  synth_rect<T, L, BC, true>(d, f, r0, r1, c0, c1, img, smem_raw, wr);
 }
 
 template <typename T, int L, int BC, int V>
 __global__ __launch_bounds__(512) void synth_level_kernel(SynthLevel d, Taps<T> f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // plain dispatch order: the XCD-aware order (xcd_tile) that speeds up the
-  // analysis and blur tiles measured 5 % slower here (2048^2 level 1)
-  synth_tile<T, L, BC, V>(d, f, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+  // XCD-aware tile order: each XCD runs a contiguous range of row-major tiles,
+  // so the halo rows and columns neighbouring tiles share stay in one L2
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  synth_tile<T, L, BC, V>(d, f, tx, ty, tz, smem_raw);
 }
 
 // One launch over tiles of several images (a tile queue): items[i] covers
@@ -166,10 +175,17 @@ __global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> 
     }
     __syncthreads();
   }
-  PlaneWriter<T> out(static_cast<T*>(c.d[0].out) + (long long)img * c.d[0].stride_out,
-                     c.d[0].c.N);
+  T* const O = static_cast<T*>(c.d[0].out) + (long long)img * c.d[0].stride_out;
   const LdsBand<T> src{reinterpret_cast<const T*>(smem_raw + c.buf_off[0]), ra[1], ca[1],
                        c.buf_pitch[0]};
+  if constexpr (sizeof(T) == 4) {
+    const SynthWin w = synth_win<L, BC>(c.d[0], ra[0], rb[0], ca[0], cb[0], img);
+    if (synth_fast_ok<L, BC, TR, TC>(c.d[0], w, O)) {
+      synth_tile_fast<L, BC, TR, true>(c.d[0], f, w, smem_raw, &src);
+      return;
+    }
+  }
+  PlaneWriter<T> out(O, c.d[0].c.N);
   synth_rect<T, L, BC>(c.d[0], f, ra[0], rb[0], ca[0], cb[0], img, smem_raw, out, &src);
 }
 

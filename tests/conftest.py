@@ -15,3 +15,12 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(autouse=True)
+def _seed_torch():
+    """Every test starts from the same torch generator state (CPU and GPU), so
+    tests that draw with torch.randn are reproducible."""
+    import torch
+    torch.manual_seed(20170706)
+    yield
