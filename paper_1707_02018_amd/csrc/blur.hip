@@ -66,6 +66,23 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
 
   const bool interior = (r0 >= R) && (r0 + TR + R <= N) && (c0 >= R) && (c0 + TC + R <= M);
 
+  // step-3 ownership (thread = one column, RB consecutive output rows); with
+  // SUB, the thread's b values are fetched first so their latency overlaps
+  // the window staging
+  constexpr int RG = NT / TC;  // row groups
+  constexpr int RB = TR / RG;  // rows per thread
+  const int pc = threadIdx.x % TC;
+  const int rg = threadIdx.x / TC;
+  const int p_c = c0 + pc;
+  T bsub[RB];
+  if (SUB) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int p_r = r0 + rg * RB + i;
+      bsub[i] = (p_r < N && p_c < M) ? SUB[img * plane + (long long)p_r * M + p_c] : T(0);
+    }
+  }
+
   // 1. stage the reflected window: rows r0-R .. r0+TR+R, cols c0-R .. c0+TC+R
   constexpr int RA = ((R + VW - 1) / VW) * VW;  // aligned left halo
   constexpr int WCV = (TC + 2 * RA) / VW;       // aligned vectors per window row
@@ -165,17 +182,12 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
 
   // 3. filter along rows: each thread owns one column and RB output rows,
   //    walked in chunks of four
-  constexpr int RG = NT / TC;  // row groups
-  constexpr int RB = TR / RG;  // rows per thread
   constexpr int CR = RB < 4 ? RB : 4;
-  const int pc = threadIdx.x % TC;
-  const int rg = threadIdx.x / TC;
-  const int p_c = c0 + pc;
   T* Yi = Y + img * plane;
   double part = 0.0;
-#pragma unroll 1
-  for (int c = 0; c < RB; c += CR) {
-    const int lr = rg * RB + c;  // first output row of the chunk (window row offset)
+  // one chunk of CR output rows from window row offset lr; bs = the chunk's
+  // b values (SUB only)
+  auto chunk = [&](int lr, const T* bs) {
     T hw[CR + 2 * R];
 #pragma unroll
     for (int i = 0; i < CR + 2 * R; ++i) hw[i] = sh[(lr + i) * TC + pc];
@@ -193,13 +205,20 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
       }
       if (p_r < N && p_c < M) {
         const long long off = (long long)p_r * M + p_c;
-        if (SUB) {
-          acc -= SUB[img * plane + off];
+        if (bs) {
+          acc -= bs[i];
           part += 0.5 * (double)acc * (double)acc;
         }
         Yi[off] = acc;
       }
     }
+  };
+  if (SUB) {  // unrolled, so the prefetched b values stay in registers
+#pragma unroll
+    for (int c = 0; c < RB; c += CR) chunk(rg * RB + c, bsub + c);
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < RB; c += CR) chunk(rg * RB + c, nullptr);
   }
   if (part_out) {
     double v[1] = {part};
