@@ -546,15 +546,24 @@ __device__ __forceinline__ void fast_col_pair(const float4* sc, float2* st, cons
   st[(2 * s + 1) * NKC + j] = make_float2(lo1, hi1);
 }
 
-// With LDSA the approximation band is read from abuf (LDS) instead of d.a.
-template <int L, int BC, int TR, bool LDSA = false>
-__device__ __forceinline__ void synth_tile_fast(const SynthLevel& d, const Taps<float>& f,
-                                                const SynthWin& w, unsigned char* smem_raw,
-                                                const LdsBand<float>* abuf = nullptr) {
+// Window of an interior tile held in registers between its loads and its LDS
+// writes: wave rows wv + 8k at lane columns, and one tail item per thread.
+template <int L, int BC, int TR>
+struct FastPre {
+  static constexpr int RPW = (FastSynth<L, BC, TR>::NKR + 7) / 8;
+  float4 q[RPW];
+  float4 qt;
+};
+
+// 1a. loads of an interior tile's window: H, V, D, and a unless LDSA (then a
+//     is taken from the LDS band by fast_stage). Wave wv loads rows wv, wv + 8,
+//     ... at lanes 0..63; the TAILC columns from 64 on go to threads
+//     0 .. NKR * TAILC - 1.
+template <int L, int BC, int TR, bool LDSA>
+__device__ __forceinline__ void fast_fetch(const SynthLevel& d, const SynthWin& w,
+                                           FastPre<L, BC, TR>& pre) {
   using G = FastSynth<L, BC, TR>;
-  constexpr int HL = G::HL, NKR = G::NKR, NKC = G::NKC, TAILC = G::TAILC, NWAVE = 8;
-  float4* sc = reinterpret_cast<float4*>(smem_raw);        // [NKR][NKC] (a, H, V, D)
-  float2* st = reinterpret_cast<float2*>(sc + NKR * NKC);  // [TR][NKC] (lo, hi)
+  constexpr int NKR = G::NKR, TAILC = G::TAILC, RPW = FastPre<L, BC, TR>::RPW;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int Kc = d.c.K;
@@ -564,49 +573,64 @@ __device__ __forceinline__ void synth_tile_fast(const SynthLevel& d, const Taps<
   const float* V = H + band;
   const float* D = V + band;
   const int base = w.kwr * Kc + w.kwc;
-
-  // 1. window: wave wv loads rows wv, wv + 8, ... at lanes 0..63; the
-  //    TAILC columns from 64 on go to threads 0 .. NKR * TAILC - 1. Every load
-  //    of a thread is issued before its LDS writes.
-  constexpr int RPW = (NKR + NWAVE - 1) / NWAVE;
-  constexpr int TAILN = NKR * TAILC;
-  float4 q[RPW];
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
-    const int i = wv + NWAVE * k;
+    const int i = wv + 8 * k;
     if (i < NKR) {
-      const int o = base + i * Kc;
-      float a;
-      if constexpr (LDSA)
-        a = abuf->p[(w.kwr + i - abuf->r0) * abuf->pitch + (w.kwc + lane - abuf->c0)];
-      else
-        a = A[o + lane];
-      q[k] = make_float4(a, H[o + lane], V[o + lane], D[o + lane]);
+      const int o = base + i * Kc + lane;
+      pre.q[k] = make_float4(LDSA ? 0.f : A[o], H[o], V[o], D[o]);
     }
   }
-  float4 qt = make_float4(0.f, 0.f, 0.f, 0.f);
-  int ti = 0, tj = 0;
-  if constexpr (TAILN > 0) {
-    if ((int)threadIdx.x < TAILN) {
-      ti = threadIdx.x / TAILC;
-      tj = 64 + (threadIdx.x - ti * TAILC);
+  if constexpr (TAILC > 0) {
+    if ((int)threadIdx.x < NKR * TAILC) {
+      const int ti = threadIdx.x / TAILC, tj = 64 + (threadIdx.x - ti * TAILC);
       const int o = base + ti * Kc + tj;
-      float a;
-      if constexpr (LDSA)
-        a = abuf->p[(w.kwr + ti - abuf->r0) * abuf->pitch + (w.kwc + tj - abuf->c0)];
-      else
-        a = A[o];
-      qt = make_float4(a, H[o], V[o], D[o]);
+      pre.qt = make_float4(LDSA ? 0.f : A[o], H[o], V[o], D[o]);
     }
   }
+}
+
+// 1b. the fetched window into LDS (with LDSA, a from abuf)
+template <int L, int BC, int TR, bool LDSA>
+__device__ __forceinline__ void fast_stage(const SynthWin& w, FastPre<L, BC, TR>& pre,
+                                           float4* sc, const LdsBand<float>* abuf) {
+  using G = FastSynth<L, BC, TR>;
+  constexpr int NKR = G::NKR, NKC = G::NKC, TAILC = G::TAILC, RPW = FastPre<L, BC, TR>::RPW;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
-    const int i = wv + NWAVE * k;
-    if (i < NKR) sc[i * NKC + lane] = q[k];
+    const int i = wv + 8 * k;
+    if (i < NKR) {
+      if constexpr (LDSA)
+        pre.q[k].x = abuf->p[(w.kwr + i - abuf->r0) * abuf->pitch + (w.kwc + lane - abuf->c0)];
+      sc[i * NKC + lane] = pre.q[k];
+    }
   }
-  if constexpr (TAILN > 0) {
-    if ((int)threadIdx.x < TAILN) sc[ti * NKC + tj] = qt;
+  if constexpr (TAILC > 0) {
+    if ((int)threadIdx.x < NKR * TAILC) {
+      const int ti = threadIdx.x / TAILC, tj = 64 + (threadIdx.x - ti * TAILC);
+      if constexpr (LDSA)
+        pre.qt.x = abuf->p[(w.kwr + ti - abuf->r0) * abuf->pitch + (w.kwc + tj - abuf->c0)];
+      sc[ti * NKC + tj] = pre.qt;
+    }
   }
+}
+
+// Steps 2 and 3 of an interior tile whose window has been fetched into pre
+// (see fast_fetch); with LDSA the approximation band is read from abuf (LDS).
+template <int L, int BC, int TR, bool LDSA = false>
+__device__ __forceinline__ void synth_tile_fast_pre(const SynthLevel& d, const Taps<float>& f,
+                                                    const SynthWin& w, unsigned char* smem_raw,
+                                                    FastPre<L, BC, TR>& pre,
+                                                    const LdsBand<float>* abuf = nullptr) {
+  using G = FastSynth<L, BC, TR>;
+  constexpr int HL = G::HL, NKR = G::NKR, NKC = G::NKC, TAILC = G::TAILC, NWAVE = 8;
+  float4* sc = reinterpret_cast<float4*>(smem_raw);        // [NKR][NKC] (a, H, V, D)
+  float2* st = reinterpret_cast<float2*>(sc + NKR * NKC);  // [TR][NKC] (lo, hi)
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  fast_stage<L, BC, TR, LDSA>(w, pre, sc, abuf);
   __syncthreads();
 
   // 2. columns: wave wv takes row pairs wv, wv + 8, ...; the pairs' tail
@@ -648,6 +672,15 @@ __device__ __forceinline__ void synth_tile_fast(const SynthLevel& d, const Taps<
     }
     *reinterpret_cast<float2*>(O + (long long)(w.r0 + pr) * d.c.N) = make_float2(o0, o1);
   }
+}
+
+template <int L, int BC, int TR, bool LDSA = false>
+__device__ __forceinline__ void synth_tile_fast(const SynthLevel& d, const Taps<float>& f,
+                                                const SynthWin& w, unsigned char* smem_raw,
+                                                const LdsBand<float>* abuf = nullptr) {
+  FastPre<L, BC, TR> pre;
+  fast_fetch<L, BC, TR, LDSA>(d, w, pre);
+  synth_tile_fast_pre<L, BC, TR, LDSA>(d, f, w, smem_raw, pre, abuf);
 }
 
 // Output of synth_rect into a row-major plane (rows of Nc values).

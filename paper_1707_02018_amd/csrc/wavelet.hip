@@ -163,6 +163,16 @@ __global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> 
     synth_axis_window(ca[k], cb[k], c.d[k].c.N, BC == SYM ? c.d[k].c.e : 0, L, BC, kw, nk);
     synth_band_part(kw, nk, c.d[k].c.K, ca[k + 1], cb[k + 1]);
   }
+  // the finest level's detail bands are fetched first when its tile takes
+  // the interior layout, so their latency overlaps the coarse levels
+  T* const O = static_cast<T*>(c.d[0].out) + (long long)img * c.d[0].stride_out;
+  const SynthWin w0 = synth_win<L, BC>(c.d[0], ra[0], rb[0], ca[0], cb[0], img);
+  bool fast0 = false;
+  FastPre<L, BC, TR> pre0;
+  if constexpr (sizeof(T) == 4) {
+    fast0 = synth_fast_ok<L, BC, TR, TC>(c.d[0], w0, O);
+    if (fast0) fast_fetch<L, BC, TR, true>(c.d[0], w0, pre0);
+  }
   for (int k = c.nl - 1; k >= 1; --k) {
     LdsWriter<T> wr{reinterpret_cast<T*>(smem_raw + c.buf_off[k - 1]), ra[k], ca[k],
                     c.buf_pitch[k - 1]};
@@ -175,13 +185,11 @@ __global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> 
     }
     __syncthreads();
   }
-  T* const O = static_cast<T*>(c.d[0].out) + (long long)img * c.d[0].stride_out;
   const LdsBand<T> src{reinterpret_cast<const T*>(smem_raw + c.buf_off[0]), ra[1], ca[1],
                        c.buf_pitch[0]};
   if constexpr (sizeof(T) == 4) {
-    const SynthWin w = synth_win<L, BC>(c.d[0], ra[0], rb[0], ca[0], cb[0], img);
-    if (synth_fast_ok<L, BC, TR, TC>(c.d[0], w, O)) {
-      synth_tile_fast<L, BC, TR, true>(c.d[0], f, w, smem_raw, &src);
+    if (fast0) {
+      synth_tile_fast_pre<L, BC, TR, true>(c.d[0], f, w0, smem_raw, pre0, &src);
       return;
     }
   }
