@@ -508,13 +508,20 @@ def main():
                  "R": 8 * npix, "R*": 8 * npix}
     dom = max(alg_bytes, key=lambda k: op_us[k])
     achieved = alg_bytes[dom] / (op_us[dom] * 1e-6) / 1e9
-    kernel_names = {"W*_level1": "ana_level_kernel<float,8,SYM>",
-                    "W_level1": "synth_level_kernel<float,8,SYM>",
-                    "R": "blur_kernel<float>", "R*": "blur_adj_kernel<float>"}
+    kernel_names = {"W*_level1": "ana_level_kernel<float,8,SYM,0>",
+                    "W_level1": "synth_level_kernel<float,8,SYM,0>",
+                    "R": "blur_tile_kernel<float,7,fwd,0>", "R*": "blur_tile_kernel<float,7,adj,0>"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom),
-                "kernel": kernel_names[dom], "algorithmic_bytes": alg_bytes[dom],
+                "kernel": kernel_names[dom], "op": dom, "algorithmic_bytes": alg_bytes[dom],
                 "avg_us": round(op_us[dom], 3)}
+    # the whole iteration against its algorithmic bytes: y and b read, r
+    # written (A y - b); r, y and x_{k-1} read, x_k and y_{k+1} written (A^*
+    # and the update)
+    step_bytes = 4 * (5 * ncoef + 3 * npix)
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
+    step_roofline = {"algorithmic_bytes": step_bytes, "achieved": round(step_gbs, 1),
+                     "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
 
     # ------------------------------------------------ time to 1e-4 (plain)
     target = None
@@ -576,6 +583,7 @@ def main():
         "ops_us": {k: round(v, 3) for k, v in op_us.items()},
         "ops_mpix_s": ops_mpix,
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "time_to_target": target,
         **extras,
         "cpu_baseline": cpu,

@@ -221,33 +221,6 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
   constexpr int KB = TKR / RBLK;
   const int kk = threadIdx.x % TKC;
   const int rb = threadIdx.x / TKC;
-  // fused update: y_k and x_{k-1} of the owned coefficients are fetched
-  // first, so their latency overlaps the staging below
-  T py[KB][4], px[KB][4];
-  if constexpr (PROX) {
-    const long long band = (long long)d.r.K * d.c.K;
-    const int kc = bx * TKC + kk;
-#pragma unroll
-    for (int r = 0; r < KB; ++r) {
-      const int kr = by * TKR + rb * KB + r;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) py[r][q] = px[r][q] = T(0);
-      if (kr < d.r.K && kc < d.c.K) {
-        const long long off = (long long)kr * d.c.K + kc;
-        const T* Y = static_cast<const T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
-        const T* X = static_cast<const T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-          py[r][q] = Y[(q - 1) * band];
-          px[r][q] = X[(q - 1) * band];
-        }
-        if (pe.x_a) {
-          py[r][0] = static_cast<const T*>(pe.y_a)[(long long)img * d.stride_a + off];
-          px[r][0] = static_cast<const T*>(pe.x_a)[(long long)img * d.stride_a + off];
-        }
-      }
-    }
-  }
   constexpr int NWR = 2 * TKR + L - 2, NWC = 2 * TKC + L - 2;
   constexpr int VW = 16 / sizeof(T);                       // elements per 16-byte LDS read
   constexpr int SUS = ((NWC + VW - 1) / VW) * VW + VW;     // input row stride
@@ -377,6 +350,34 @@ __device__ __forceinline__ void ana_tile(const AnaLevel& d, const Taps<T>& f, in
   }
   __syncthreads();
 
+  // fused update: y_k and x_{k-1} of the owned coefficients are fetched once
+  // the window is staged, so their latency overlaps the column pass (fetched
+  // before the staging, they held registers that cost a workgroup per CU)
+  T py[KB][4], px[KB][4];
+  if constexpr (PROX) {
+    const long long band = (long long)d.r.K * d.c.K;
+    const int kc = bx * TKC + kk;
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+      const int kr = by * TKR + rb * KB + r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) py[r][q] = px[r][q] = T(0);
+      if (kr < d.r.K && kc < d.c.K) {
+        const long long off = (long long)kr * d.c.K + kc;
+        const T* Y = static_cast<const T*>(pe.y_hvd) + (long long)img * d.stride_hvd + off;
+        const T* X = static_cast<const T*>(pe.x_hvd) + (long long)img * d.stride_hvd + off;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          py[r][q] = Y[(q - 1) * band];
+          px[r][q] = X[(q - 1) * band];
+        }
+        if (pe.x_a) {
+          py[r][0] = static_cast<const T*>(pe.y_a)[(long long)img * d.stride_a + off];
+          px[r][0] = static_cast<const T*>(pe.x_a)[(long long)img * d.stride_a + off];
+        }
+      }
+    }
+  }
   // 2. filter along columns, two output columns per item:
   //    (lo, hi)[i][kc] = sum_j (h, g)[j] u(i, 2 kc + j)
   constexpr int CP = TKC / 2;
