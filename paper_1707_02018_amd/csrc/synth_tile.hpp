@@ -617,36 +617,35 @@ __device__ __forceinline__ void fast_stage(const SynthWin& w, FastPre<L, BC, TR>
   }
 }
 
-// Steps 2 and 3 of an interior tile whose window has been fetched into pre
-// (see fast_fetch); with LDSA the approximation band is read from abuf (LDS).
-template <int L, int BC, int TR, bool LDSA = false>
-__device__ __forceinline__ void synth_tile_fast_pre(const SynthLevel& d, const Taps<float>& f,
-                                                    const SynthWin& w, unsigned char* smem_raw,
-                                                    FastPre<L, BC, TR>& pre,
-                                                    const LdsBand<float>* abuf = nullptr) {
+// 2. columns of an interior tile from its staged window: wave wv takes row
+//    pairs wv, wv + 8, ...; the pairs' tail columns go to threads
+//    0 .. TR / 2 * TAILC - 1
+template <int L, int BC, int TR>
+__device__ __forceinline__ void fast_columns(const float4* sc, float2* st, const Taps<float>& f) {
   using G = FastSynth<L, BC, TR>;
-  constexpr int HL = G::HL, NKR = G::NKR, NKC = G::NKC, TAILC = G::TAILC, NWAVE = 8;
-  float4* sc = reinterpret_cast<float4*>(smem_raw);        // [NKR][NKC] (a, H, V, D)
-  float2* st = reinterpret_cast<float2*>(sc + NKR * NKC);  // [TR][NKC] (lo, hi)
+  constexpr int TAILC = G::TAILC;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  fast_stage<L, BC, TR, LDSA>(w, pre, sc, abuf);
-  __syncthreads();
-
-  // 2. columns: wave wv takes row pairs wv, wv + 8, ...; the pairs' tail
-  //    columns go to threads 0 .. TR / 2 * TAILC - 1
-  for (int s = wv; s < TR / 2; s += NWAVE) fast_col_pair<L, BC, TR>(sc, st, f, s, lane);
+  for (int s = wv; s < TR / 2; s += 8) fast_col_pair<L, BC, TR>(sc, st, f, s, lane);
   if constexpr (TAILC > 0) {
     for (int item = threadIdx.x; item < TR / 2 * TAILC; item += 512) {
       const int s = item / TAILC;
       fast_col_pair<L, BC, TR>(sc, st, f, s, 64 + (item - s * TAILC));
     }
   }
-  __syncthreads();
+}
 
-  // 3. rows: wave wv takes output rows wv, wv + 8, ...; lane = output pair
+// 3. rows of an interior tile: wave wv takes output rows wv, wv + 8, ...;
+//    lane = output pair
+template <int L, int BC, int TR>
+__device__ __forceinline__ void fast_rows(const SynthLevel& d, const SynthWin& w, const float2* st,
+                                          const Taps<float>& f) {
+  using G = FastSynth<L, BC, TR>;
+  constexpr int HL = G::HL, NKC = G::NKC;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* O = static_cast<float*>(d.out) + (long long)w.img * d.stride_out + w.c0 + 2 * lane;
-  for (int pr = wv; pr < TR; pr += NWAVE) {
+  for (int pr = wv; pr < TR; pr += 8) {
     const float2* row = st + pr * NKC + lane;
     float o0 = 0.f, o1 = 0.f;
     if constexpr (G::SHIFT) {
@@ -672,6 +671,23 @@ __device__ __forceinline__ void synth_tile_fast_pre(const SynthLevel& d, const T
     }
     *reinterpret_cast<float2*>(O + (long long)(w.r0 + pr) * d.c.N) = make_float2(o0, o1);
   }
+}
+
+// Steps 1b, 2 and 3 of an interior tile whose window has been fetched into
+// pre (see fast_fetch); with LDSA the approximation band is read from abuf.
+template <int L, int BC, int TR, bool LDSA = false>
+__device__ __forceinline__ void synth_tile_fast_pre(const SynthLevel& d, const Taps<float>& f,
+                                                    const SynthWin& w, unsigned char* smem_raw,
+                                                    FastPre<L, BC, TR>& pre,
+                                                    const LdsBand<float>* abuf = nullptr) {
+  using G = FastSynth<L, BC, TR>;
+  float4* sc = reinterpret_cast<float4*>(smem_raw);              // [NKR][NKC] (a, H, V, D)
+  float2* st = reinterpret_cast<float2*>(sc + G::NKR * G::NKC);  // [TR][NKC] (lo, hi)
+  fast_stage<L, BC, TR, LDSA>(w, pre, sc, abuf);
+  __syncthreads();
+  fast_columns<L, BC, TR>(sc, st, f);
+  __syncthreads();
+  fast_rows<L, BC, TR>(d, w, st, f);
 }
 
 template <int L, int BC, int TR, bool LDSA = false>
