@@ -40,6 +40,7 @@ PMC_KERNELS = {
     "W*_level1": ("void aw::ana_level_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
     "R": ("void aw::blur_tile_kernel<float, 7, false, 0>", 524288, "blur.hip"),
     "R*": ("void aw::blur_tile_kernel<float, 7, true, 0>", 524288, "blur.hip"),
+    "W*prox_level1": ("void aw::ana_prox_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fista2048_sym.md")
 
@@ -476,6 +477,15 @@ def main():
     ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
     w1 = ops.WaveletSpec(N, N, 1, taps=8, bc=args.bc)  # level 1 alone: one kernel
     P = lambda t: ops._ptr(t)  # noqa: E731
+    # the update half of the iteration at level 1 alone (one kernel: W^* of an
+    # image-space gradient with the proximal / momentum update of all four
+    # level-1 bands), on its own state
+    x1 = torch.randn(w1.ncoef, device=dev) * 1e-2
+    y1 = torch.randn(w1.ncoef, device=dev) * 1e-2
+    st1 = _lib.FistaState()
+    st1.x, st1.y, st1.resid, st1.obj = x1.data_ptr(), y1.data_ptr(), None, None
+    st1.k, st1.t, st1.gradient = 1, 1.0, 0
+    ctypes_ = __import__("ctypes")
 
     def make_calls(s):
         sp = __import__("ctypes").c_void_p(s.cuda_stream)
@@ -494,6 +504,8 @@ def main():
             "W*_level1": lambda: lib.wavelet_synth_adjoint(w1.c, 0, 1, P(y), P(out_coef), P(ws),
                                                            wsn, sp),
             "W_level1": lambda: lib.wavelet_synth(w1.c, 0, 1, P(x), P(out_img), P(ws), wsn, sp),
+            "W*prox_level1": lambda: lib.aw_fista_update(w1.c, 0, 1, P(y), 1.0, lam,
+                                                         ctypes_.byref(st1), 0, P(ws), wsn, sp),
         }
 
     with torch.cuda.stream(stream):
@@ -501,16 +513,19 @@ def main():
         op_us = {name: graph_us(torch, stream, fn, name) for name, fn in calls.items()}
     ops_mpix = {k: round(npix / v, 1) for k, v in op_us.items()}
 
-    # dominant single-kernel operator: level-1 analysis (W^* at level 1) or R / R^*
+    # dominant single-kernel operator of the step that bench.py can time alone:
+    # the level-1 synthesis or analysis, R, R^*, or the level-1 update (the
+    # image in; x_{k-1}, y_k read and x_k, y_{k+1} written for the four bands)
     _, sr, sc = w.layout()
     k1 = sr[1] * sc[1]
     alg_bytes = {"W*_level1": 4 * (npix + 4 * k1), "W_level1": 4 * (npix + 4 * k1),
-                 "R": 8 * npix, "R*": 8 * npix}
+                 "R": 8 * npix, "R*": 8 * npix, "W*prox_level1": 4 * (npix + 16 * k1)}
     dom = max(alg_bytes, key=lambda k: op_us[k])
     achieved = alg_bytes[dom] / (op_us[dom] * 1e-6) / 1e9
     kernel_names = {"W*_level1": "ana_level_kernel<float,8,SYM,0>",
                     "W_level1": "synth_level_kernel<float,8,SYM,0>",
-                    "R": "blur_tile_kernel<float,7,fwd,0>", "R*": "blur_tile_kernel<float,7,adj,0>"}
+                    "R": "blur_tile_kernel<float,7,fwd,0>", "R*": "blur_tile_kernel<float,7,adj,0>",
+                    "W*prox_level1": "ana_prox_kernel<float,8,SYM,0>"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom),
                 "kernel": kernel_names[dom], "op": dom, "algorithmic_bytes": alg_bytes[dom],

@@ -304,6 +304,22 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
                      int32_t want_objective, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* The second half of fista_step, from an image-space gradient: with
+ * grad = R^*(A y_k - b) (or the gradient of any other smooth term in image
+ * space), the coefficient gradient W^* grad (W^dagger grad with
+ * AW_GRAD_PINV) is consumed level by level by the update
+ *   x_k = soft(y_k - W^* grad / L, lambda/L),  y_{k+1} = x_k + beta_k (x_k - x_{k-1}),
+ * with t_k, beta_k and the state's k, t advanced as in fista_step (Beck &
+ * Teboulle's step as used in Sec. "Example 1: An Image Deblurring Problem").
+ * grad is a device image [batch][rows][cols] (read only); state->resid and
+ * the blur are not used. With want_l1 and state->obj, obj[2i+1] = ||x_k||_1
+ * (obj[2i] untouched). The workspace is sized by aw_workspace_size(w, NULL,
+ * ...). Fails with AW_EINVAL on NULL pointers, batch < 1, L <= 0, lambda < 0,
+ * k < 1, t < 1 or an unknown gradient map. */
+aw_status aw_fista_update(const aw_wavelet* w, aw_dtype dtype, int32_t batch, const void* grad,
+                          double L, double lambda, aw_fista_state* state, int32_t want_l1,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 /* Objective of eq. (1) at x: obj[3i] = 1/2 ||A x_i - b_i||^2,
  * obj[3i+1] = ||x_i||_1, obj[3i+2] = obj[3i] + lambda obj[3i+1]
  * (obj: device doubles [batch][3]; fixed-order reductions, reproducible). */

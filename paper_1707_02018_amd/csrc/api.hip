@@ -759,6 +759,42 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   return ok();
 }
 
+aw_status aw_fista_update(const aw_wavelet* w, aw_dtype dtype, int32_t batch, const void* grad,
+                          double L, double lambda, aw_fista_state* state, int32_t want_l1,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  WavePlan p;
+  aw_status st;
+  if (!state) return fail(AW_EINVAL, "state is NULL");
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if ((st = make_plan(w, p)) != AW_OK) return st;
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  if (!grad || !state->x || !state->y) return fail(AW_EINVAL, "NULL data pointer");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(AW_EINVAL, "L=%g", L);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
+  if (state->k < 1) return fail(AW_EINVAL, "k=%lld (iterations count from 1)", (long long)state->k);
+  if (!(state->t >= 1.0)) return fail(AW_EINVAL, "t=%g (t_1 = 1, increasing)", state->t);
+  if (state->gradient != AW_GRAD_ADJOINT && state->gradient != AW_GRAD_PINV)
+    return fail(AW_EINVAL, "gradient=%d (AW_GRAD_ADJOINT or AW_GRAD_PINV)", (int)state->gradient);
+  const WsLayout l = layout_ws(&p, nullptr, dtype, batch);
+  if ((st = need_ws(workspace, workspace_bytes, l.total)) != AW_OK) return st;
+  const bool l1 = want_l1 && state->obj;
+  hipStream_t s = (hipStream_t)stream;
+  double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
+  const double t = state->t;
+  const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+  const double beta = (t - 1.0) / tn;
+  const int fold_w = state->gradient == AW_GRAD_PINV ? 0 : 1;
+  if ((st = run_analysis_prox(p, dtype, batch, grad, state->x, state->y, workspace, l, 1.0 / L,
+                              lambda / L, beta, l1 ? pl : nullptr, fold_w, s)) != AW_OK)
+    return st;
+  if (l1 && (st = hip_check(aw::launch_reduce_partials(batch, l.n_pt, pl, 1.0, state->obj, 2, 1, s),
+                            "reduce launch")) != AW_OK)
+    return st;
+  state->t = tn;
+  state->k += 1;
+  return ok();
+}
+
 aw_status aw_objective(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
                        const void* b_obs, double lambda, const void* x, double* obj,
                        void* workspace, size_t workspace_bytes, void* stream) {

@@ -393,6 +393,23 @@ def fista_step(state: FistaState, b_obs: torch.Tensor, lam: float, L: float = 1.
     state.k, state.t = int(cs.k), float(cs.t)
 
 
+def fista_update(state: FistaState, grad: torch.Tensor, lam: float, L: float = 1.0,
+                 want_l1: bool = False) -> None:
+    """The update half of a FISTA iteration from an image-space gradient
+    grad (R^*(A y - b) for eq. (1)): x, y, k, t of the state advance as in
+    fista_step; with want_l1, state.obj[:, 1] = ||x_k||_1."""
+    _dev(grad)
+    if _batch_img(grad, state.w.rows, state.w.cols) != state.batch:
+        raise ValueError("grad batch differs from the state's")
+    cs = state.c_state()
+    ws, n = _workspace(state.w, None, grad, state.batch)
+    check("aw_fista_update", load().aw_fista_update(state.w.c, _dtype_code(grad), state.batch,
+                                                    _ptr(grad), float(L), float(lam),
+                                                    ctypes.byref(cs), int(bool(want_l1)),
+                                                    _ptr(ws), n, _stream(grad)))
+    state.k, state.t = int(cs.k), float(cs.t)
+
+
 def objective(w: WaveletSpec, b: BlurSpec, b_obs: torch.Tensor, x: torch.Tensor, lam: float,
               out: torch.Tensor | None = None) -> torch.Tensor:
     """[batch, 3] FP64 device tensor: 1/2||Ax-b||^2, ||x||_1, F(x) (eq. 1)."""

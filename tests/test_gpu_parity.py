@@ -323,3 +323,79 @@ def test_conv_pair_full_size_sampled():
         assert rel(r[p], r_ref[0]) <= 1e-5
         assert rel(gh[p], gh_ref[0]) <= 1e-5
         assert rel(gs[p], gs_ref[0]) <= 1e-5
+
+
+@pytest.mark.parametrize("mode,gradient", [("sym", "adjoint"), ("sym", "pinv"),
+                                           ("zpd", "adjoint"), ("per", "adjoint"),
+                                           ("per_ext", "adjoint")])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_fista_update_from_image_gradient(dt, mode, gradient):
+    """The update half of the iteration (aw_fista_update) from an arbitrary
+    image-space gradient g: x_k = soft(y - W^* g / L, lambda / L) (W^dagger g
+    for the pinv map) and the momentum step, against the oracle; then, fed
+    R^*(A y - b) as fista_step forms it, bitwise equal to fista_step."""
+    print(f"[fista update] 96x80 {dt} mode={mode} gradient={gradient}", flush=True)
+    rows, cols, J, L = 96, 80, 3, 2.0
+    h = ofl.by_taps(8)
+    rng = rng_for(6, 1)
+    n = owv.layout(rows, cols, 8, mode, J)[0]
+    x_prev = rng.standard_normal(n) * 1e-2
+    y = rng.standard_normal(n) * 1e-2
+    g = rng.standard_normal((rows, cols))
+    lam, k, t = 3e-3, 4, 2.0
+    tn = ofi.t_next(t)
+    beta = (t - 1.0) / tn
+    gc = owv.W_adj(g, h, mode, J) if gradient == "adjoint" else owv.W_pinv(g, h, mode, J)
+    x_ref = ofi.soft(y - gc / L, lam / L)
+    y_ref = x_ref + beta * (x_ref - x_prev)
+    w = ops.WaveletSpec(rows, cols, J, lo=h, bc=mode)
+    bs = ops.BlurSpec(rows, cols, taps=obl.gaussian_taps(1.5, 3))
+    b0 = torch.zeros(rows, cols, dtype=dt, device=DEV)
+    st = ops.FistaState(w, bs, b0, x0=dev(x_prev, dt), gradient=gradient)
+    st.y.copy_(dev(y, dt))
+    st.k, st.t = k, t
+    ops.fista_update(st, dev(g, dt), lam, L=L, want_l1=True)
+    tol = TOL[dt]
+    assert rel(host(st.x), x_ref) <= tol
+    assert rel(host(st.y), y_ref) <= tol
+    l1 = host(st.obj)[0][1]
+    assert abs(l1 - np.sum(np.abs(x_ref))) <= tol * np.sum(np.abs(x_ref))
+    assert st.k == k + 1 and abs(st.t - tn) < 1e-15
+
+    # fed R^*(A y - b) as fista_step forms it: the same kernels, the same bits
+    b_obs = dev(gen_image(rng, rows, cols), dt)
+    sa = ops.FistaState(w, bs, b_obs, x0=dev(x_prev, dt), gradient=gradient)
+    sb = ops.FistaState(w, bs, b_obs, x0=dev(x_prev, dt), gradient=gradient)
+    for s_ in (sa, sb):
+        s_.y.copy_(dev(y, dt))
+        s_.k, s_.t = k, t
+    ops.fista_step(sa, b_obs, lam, L=L)
+    ops.fista_update(sb, ops.blur_adjoint(bs, sa.resid), lam, L=L)
+    torch.cuda.synchronize()
+    assert torch.equal(sa.x, sb.x) and torch.equal(sa.y, sb.y)
+    assert (sa.k, sa.t) == (sb.k, sb.t)
+
+
+def test_fista_update_rejects_bad_arguments():
+    """Host-side validation before any launch: bad L, lambda, k, t and a
+    gradient of the wrong batch."""
+    w = ops.WaveletSpec(64, 64, 2, taps=8, bc="sym")
+    bs = ops.BlurSpec(64, 64, sigma=1.0, radius=3)
+    b0 = torch.zeros(64, 64, device=DEV)
+    st = ops.FistaState(w, bs, b0)
+    g = torch.zeros(64, 64, device=DEV)
+    for kw in ({"L": 0.0}, {"L": float("nan")}):
+        with pytest.raises(RuntimeError):
+            ops.fista_update(st, g, 1e-3, **kw)
+    with pytest.raises(RuntimeError):
+        ops.fista_update(st, g, -1.0)
+    st.k = 0
+    with pytest.raises(RuntimeError):
+        ops.fista_update(st, g, 1e-3)
+    st.k, st.t = 1, 0.5
+    with pytest.raises(RuntimeError):
+        ops.fista_update(st, g, 1e-3)
+    st.t = 1.0
+    with pytest.raises(ValueError):
+        ops.fista_update(st, torch.zeros(2, 64, 64, device=DEV), 1e-3)
+    assert st.k == 1 and st.t == 1.0
