@@ -476,17 +476,32 @@ prob = fi.Problem({size}, {size}, fl.by_taps(8), {bc!r}, 4, psf)
 t0 = time.perf_counter()
 fi.fista(prob, b, 2e-5, {iters})
 dt = time.perf_counter() - t0
-print(json.dumps({{"sec_per_iter": dt / {iters}}}))
+from oracle import wavelet as wv
+h = fl.by_taps(8)
+x = np.random.default_rng(0).standard_normal(prob.ncoef) * 1e-2
+ops = {{"W": lambda: wv.W(x, h, {bc!r}, 4, {size}, {size}),
+       "W*": lambda: wv.W_adj(img, h, {bc!r}, 4),
+       "R": lambda: bl.R(img, psf), "R*": lambda: bl.R_adj(img, psf),
+       "A": lambda: prob.A(x), "A*": lambda: prob.A_adj(img)}}
+op_s = {{}}
+for name, fn in ops.items():
+    t1 = time.perf_counter()
+    fn()
+    op_s[name] = time.perf_counter() - t1
+print(json.dumps({{"sec_per_iter": dt / {iters}, "op_s": op_s}}))
 """
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
                          timeout=600)
     if out.returncode != 0:
         return {"error": out.stderr[-500:]}
-    spi = json.loads(out.stdout.strip().splitlines()[-1])["sec_per_iter"]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    spi = res["sec_per_iter"]
     return {"value": size * size / spi / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} FISTA iterations (one A and one A* each) at {size}x{size}, "
-                      f"FP64 NumPy, single thread; {spi:.2f} s/iteration"}
+                      f"FP64 NumPy, single thread; {spi:.2f} s/iteration",
+            "ops_mpix_s": {k: round(size * size / v / 1e6, 3) for k, v in res["op_s"].items()},
+            "ops_sample": "one application each of W, W*, R, R*, A, A* at the same size"}
 
 
 def main():
