@@ -399,3 +399,28 @@ def test_fista_update_rejects_bad_arguments():
     with pytest.raises(ValueError):
         ops.fista_update(st, torch.zeros(2, 64, 64, device=DEV), 1e-3)
     assert st.k == 1 and st.t == 1.0
+
+
+@pytest.mark.parametrize("taps", [2, 8, 10, 16])
+@pytest.mark.parametrize("mode", ["sym", "zpd", "per"])
+def test_interior_and_border_synthesis_tiles(taps, mode):
+    """W at sizes with interior synthesis tiles (the wave-per-row layout) and
+    border / ragged tiles (the general loops) side by side, for every filter
+    length (10 = CDF 9/7) and the modes with interior tiles; J = 2 runs the
+    level kernel alone, J = 4 the chained coarse levels too. FP32 against
+    the oracle on the whole output, and W^* by the dot test."""
+    rows, cols = 528, 704  # every level even for per; interior and ragged tiles
+    print(f"[tiles] {rows}x{cols} taps={taps} mode={mode}", flush=True)
+    h = ofl.cdf97() if taps == 10 else ofl.by_taps(taps)
+    fam = {"family": "cdf97"} if taps == 10 else {"taps": taps}
+    for J in (2, 4):
+        n = owv.layout(rows, cols, taps, mode, J)[0]
+        rng = rng_for(97, taps * 10 + J)
+        x = rng.standard_normal(n)
+        y = rng.standard_normal((rows, cols))
+        w = ops.WaveletSpec(rows, cols, J, bc=mode, **fam)
+        xd, yd = dev(x, torch.float32), dev(y, torch.float32)
+        f = host(ops.wavelet_synth(w, xd))
+        assert rel(f, owv.W(x, h, mode, J, rows, cols)) <= 1e-5, J
+        a = host(ops.wavelet_synth_adjoint(w, yd))
+        assert dot_test(f, host(xd), a, host(yd)) <= 1e-6, J
