@@ -10,8 +10,9 @@ namespace aw {
 
 // Tile shapes; variant 1 halves the rows (more, smaller tiles for small
 // levels). The batched path picks the variant per launch (autotuned). FP32
-// tiles are 32 x 128: at 2048^2 the level-1 synthesis ran 13.8 us against
-// 16.0 us with 32 x 64 (32 x 256, 64 x 128, 16 x 128 and 16 x 256 were slower).
+// tiles are 32 x 128 (at 2048^2 faster than 32 x 64, 32 x 256, 64 x 128,
+// 16 x 128 and 16 x 256); 128 columns are the 64 lanes' output pairs of the
+// interior layout below.
 template <typename T, int V = 0>
 struct SynthTile {
   static constexpr int TR = (sizeof(T) == 4 ? 32 : 16) >> V, TC = sizeof(T) == 4 ? 128 : 64;
