@@ -194,7 +194,7 @@ __global__ __launch_bounds__(512) void synth_chain_kernel(SynthChain c, Taps<T> 
     }
   }
   PlaneWriter<T> out(O, c.d[0].c.N);
-  synth_rect<T, L, BC>(c.d[0], f, ra[0], rb[0], ca[0], cb[0], img, smem_raw, out, &src);
+  synth_rect<T, L, BC, true>(c.d[0], f, ra[0], rb[0], ca[0], cb[0], img, smem_raw, out, &src);
 }
 
 // Largest output part, and coefficient window, of each chained level over
