@@ -129,6 +129,20 @@ def test_entry_points_validate_before_launch(lib):
     st.k = 1
     assert lib.fista_step(W, B, 0, 1, dummy, 0.0, 2e-5, ctypes.byref(st), 0, ws, 1 << 30,
                           None) == _lib.EINVAL  # L = 0
+    S = ctypes.byref(st)
+    assert lib.aw_fista_update(W, 0, 1, dummy, 1.0, 2e-5, None, 0, ws, 1 << 30,
+                               None) == _lib.EINVAL  # no state
+    assert lib.aw_fista_update(W, 0, 1, None, 1.0, 2e-5, S, 0, ws, 1 << 30,
+                               None) == _lib.EINVAL  # no gradient
+    assert lib.aw_fista_update(W, 0, 1, dummy, 1.0, -1.0, S, 0, ws, 1 << 30,
+                               None) == _lib.EINVAL  # lambda < 0
+    assert lib.aw_fista_update(W, 0, 1, dummy, 1.0, 2e-5, S, 0, ws, 16,
+                               None) == _lib.EINVAL  # small workspace
+    st.gradient = 5
+    assert lib.aw_fista_update(W, 0, 1, dummy, 1.0, 2e-5, S, 0, ws, 1 << 30,
+                               None) == _lib.EINVAL  # unknown gradient map
+    st.gradient = 0
+    assert st.k == 1 and st.t == 1.0  # a rejected call advances nothing
     assert lib.conv_adjoint_pair(0, 1, 0, 5, dummy, dummy, None, ws, None, None,
                                  None) == _lib.EINVAL
     assert lib.conv_adjoint_pair(0, 1, 3, 5, dummy, ws, None, ws, None, None,
