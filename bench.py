@@ -226,7 +226,11 @@ def bench_conv(torch, ops) -> dict:
     flops = 2.0 * B * (K * N * 3)  # h*s, S^* r and H^* r: K N multiply-adds each
     return {"pairs": B, "K": K, "N": N, "ms": round(ms, 3),
             "GFLOPs": round(flops / (ms * 1e-3) / 1e9, 1),
-            "frac_fp32_vector_peak_157T": round(flops / (ms * 1e-3) / 157.3e12, 4)}
+            "frac_fp32_vector_peak_157T": round(flops / (ms * 1e-3) / 157.3e12, 4),
+            # the kernels are built without packed FP32 instructions, whose
+            # dual-issue the 157.3 TFLOP/s figure counts: one FMA per lane and
+            # cycle gives half of it
+            "frac_unpacked_fp32_78T": round(flops / (ms * 1e-3) / 78.65e12, 4)}
 
 
 def bench_warm(torch, ops, n_images: int) -> dict:
