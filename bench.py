@@ -124,6 +124,8 @@ def parse():
     ap.add_argument("--batched-iters", type=int, default=300)
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the uneven-batch section and print its JSON (for profiling)")
+    ap.add_argument("--only-conv", action="store_true",
+                    help="run only the convolution-pair section and print its JSON (for profiling)")
     ap.add_argument("--warm-images", type=int, default=16)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print traffic records from two rocprofv3 --pmc counter CSVs "
@@ -530,6 +532,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.only_batched:
         print(json.dumps(bench_batched(torch, ops, args.batched_iters)))
+        return
+    if args.only_conv:
+        print(json.dumps(bench_conv(torch, ops)))
         return
     if args.copy_reference:
         src = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device=dev)

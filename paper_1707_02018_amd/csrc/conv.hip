@@ -155,14 +155,39 @@ __global__ __launch_bounds__(kLagThreads) void corr_long_kernel(int K, int N, lo
 #pragma unroll
   for (int l = 0; l < 8; ++l) acc[l] = T(0);
 
+  // The grid holds one workgroup per pair and lag block (256 at the benchmark
+  // shape, one per CU), so nothing else hides the latency of the chunk loads:
+  // the next chunk is fetched into registers while the current one is used.
+  constexpr int QS = CH / kLagThreads;
+  constexpr int RW = CH + kLagBlock + 7;
+  constexpr int QR = (RW + kLagThreads - 1) / kLagThreads;
+  static_assert(CH % kLagThreads == 0, "s chunk splits evenly over the threads");
+  T ps[QS], pr[QR];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int i = threadIdx.x + q * kLagThreads;
+      ps[q] = (c0 + i < N) ? S[c0 + i] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+      const int i = threadIdx.x + q * kLagThreads;
+      const int ri = c0 + n0 + i;
+      pr[q] = (i < RW && ri < R) ? Rr[ri] : T(0);
+    }
+  };
+  fetch(0);
   for (int c0 = 0; c0 < N; c0 += CH) {
     __syncthreads();
-    for (int i = threadIdx.x; i < CH; i += kLagThreads) ss[i] = (c0 + i < N) ? S[c0 + i] : T(0);
-    for (int i = threadIdx.x; i < CH + kLagBlock + 7; i += kLagThreads) {
-      const int ri = c0 + n0 + i;
-      sr[i] = (ri < R) ? Rr[ri] : T(0);
+#pragma unroll
+    for (int q = 0; q < QS; ++q) ss[threadIdx.x + q * kLagThreads] = ps[q];
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+      const int i = threadIdx.x + q * kLagThreads;
+      if (i < RW) sr[i] = pr[q];
     }
     __syncthreads();
+    if (c0 + CH < N) fetch(c0 + CH);
     const int kb = ks * SL;
     for (int kg = 0; kg < SL; kg += 8) {
       T V[15], Sv[8];
