@@ -685,7 +685,7 @@ def main():
         extras["blur_dct"] = bench_blur_dct(torch, ops, lib, stream)
         log("adjoint vs pseudoinverse gradient (256^2, 2500 iterations)")
         extras["adjoint_vs_pinv"] = bench_adjoint_study()
-        log("multi-channel blind channel estimation (eq. 7, up to 10,000 iterations)")
+        log("multi-channel blind channel estimation (eq. 6, up to 10,000 iterations)")
         extras["blind_channel"] = bench_blind()
     log("cpu baseline")
 

@@ -232,7 +232,7 @@ aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dty
 
 /* ------------------------------- multi-channel blind channel estimation */
 
-/* Sec. "Example 2", eq. 7: C channels h_c (length K) observe one source s
+/* Sec. "Example 2", eq. 6: C channels h_c (length K) observe one source s
  * (length N); x_c = h_c * s (full linear convolution, length M = K+N-1).
  * For all channels at once:
  *   resid[c]        = h_c * s - x_obs[c]   (x_obs NULL: no subtraction)
@@ -242,14 +242,14 @@ aw_status aw_apply_A_adjoint_fused(const aw_wavelet* w, const aw_blur* b, aw_dty
  *   rnorm[c]        = ||resid[c]||^2 (device doubles)
  * h [C][K], x_obs and resid [C][M], grad_s_parts [C][N], s and grad_s [N];
  * grad_h, grad_s_parts, grad_s and rnorm may be NULL. These are the gradients
- * of 1/2 ||h_c * s - x_c||^2 (the data term of eq. 7 carries no 1/2: its
+ * of 1/2 ||h_c * s - x_c||^2 (the data term of eq. 6 carries no 1/2: its
  * gradients are twice these). resid must not alias the inputs. */
 aw_status aw_conv_multichannel(aw_dtype dtype, int32_t channels, int32_t K, int32_t N,
                                const void* h, const void* s, const void* x_obs, void* resid,
                                void* grad_h, void* grad_s_parts, void* grad_s, double* rnorm,
                                void* stream);
 
-/* The softened TV term of eq. 7 per row b of h [batch][K]:
+/* The softened TV term of eq. 6 per row b of h [batch][K]:
  *   value[b] = sum_{j<K-1} L_delta((D h_b)_j),  (D h)_j = h_{j+1} - h_j,
  *   L_delta(z) = z^2/2 (|z| <= delta), delta (|z| - delta/2) otherwise,
  *   grad[b][j] += gscale * (D^* clip(D h_b, -delta, delta))_j,

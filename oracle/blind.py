@@ -3,7 +3,7 @@
 
 Sec. "Example 2": C channels h_c (length K each) observe one source s
 (length N), x_c = h_c * s + noise (full linear convolution, length K+N-1).
-The augmented problem (eq. 7) is
+The augmented problem (eq. 6) is
 
     min_{h, s}  sum_c [ f_delta(h_c, s) + lambda_h ||h_c||_1 ] + lambda_s ||s||_1,
     f_delta(h_c, s) = ||h_c * s - x_c||^2 + lambda_tv L_delta(D h_c) / delta,
@@ -75,7 +75,7 @@ def grad_smooth(h, s, x, lam_tv: float, delta: float):
 
 
 def objective(h, s, x, p: dict) -> float:
-    """The objective of eq. 7; p holds lam_h, lam_s, lam_tv, delta."""
+    """The objective of eq. 6; p holds lam_h, lam_s, lam_tv, delta."""
     return (smooth(h, s, x, p["lam_tv"], p["delta"]) + p["lam_h"] * float(np.sum(np.abs(h)))
             + p["lam_s"] * float(np.sum(np.abs(s))))
 

@@ -1,5 +1,5 @@
 """Multi-channel blind channel estimation with a Huber TV term (Sec. "Example
-2", eq. 7) on the GPU.
+2", eq. 6) on the GPU.
 
     min_{h, s}  sum_c [ ||h_c * s - x_c||^2 + (lambda_tv / delta) L_delta(D h_c)
                         + lambda_h ||h_c||_1 ] + lambda_s ||s||_1
@@ -98,7 +98,7 @@ class BlindChannel:
 
     # ----------------------------------------------------------- solver
     def step(self) -> float:
-        """One alternating iteration; returns the objective of eq. 7 after it."""
+        """One alternating iteration; returns the objective of eq. 6 after it."""
         p = self.p
         # h block: gradient 2 (S^* r + lambda_tv / (2 delta) D^* clip(D h))
         self._conv(self.h, self.s, grad_h=self.gh)
@@ -142,7 +142,7 @@ class BlindChannel:
         return self._read()[2][2]
 
     def objective(self) -> float:
-        """The objective of eq. 7 at the current (h, s)."""
+        """The objective of eq. 6 at the current (h, s)."""
         self._conv(self.h, self.s)
         self._huber(self.h)
         rn, tv, _ = self._read()

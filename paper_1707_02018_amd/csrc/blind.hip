@@ -1,5 +1,5 @@
 // Multi-channel blind channel estimation with a Huber total variation term
-// (Sec. "Example 2", eq. 7), gfx950: the pieces a first-order solver needs
+// (Sec. "Example 2", eq. 6), gfx950: the pieces a first-order solver needs
 // besides the convolution pair (conv.hip).
 //
 //   sum_rows   out[n] = sum_c in[c][n], channels in order (the source gradient

@@ -1,4 +1,4 @@
-"""Multi-channel blind channel estimation on the GPU (Sec. "Example 2", eq. 7):
+"""Multi-channel blind channel estimation on the GPU (Sec. "Example 2", eq. 6):
 the shared-source convolution pair, the Huber TV term and the proximal step
 against the FP64 oracle; the alternating solver's trajectory (objective and
 step sizes, iteration by iteration) against the oracle's in FP64; FP32

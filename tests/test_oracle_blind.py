@@ -1,4 +1,4 @@
-"""Pins for the oracle's multi-channel blind channel estimation (eq. 7): the
+"""Pins for the oracle's multi-channel blind channel estimation (eq. 6): the
 Huber function's closed forms and TV limit, D^* = D^T, a hand-computed
 objective, gradients by finite differences, and the solver's descent and
 fixed point (CPU only)."""

@@ -20,6 +20,38 @@ def blur_adj_matrix_1d(N, taps):
 
 
 # ---------------------------------------------------------------------- R
+def test_gaussian_taps_hand_value():
+    """The width convention exp(-u^2 / (2 sigma^2)): at sigma = 1, r = 1 the
+    taps are (e^{-1/2}, 1, e^{-1/2}) / (1 + 2 e^{-1/2}), computed by hand.
+    A slip such as exp(-u^2 / sigma^2) gives (e^{-1}, 1, e^{-1}) / (1 + 2/e)."""
+    e = np.exp(-0.5)
+    want = np.array([e, 1.0, e]) / (1.0 + 2.0 * e)
+    np.testing.assert_allclose(bl.gaussian_taps(1.0, 1), want, rtol=0, atol=1e-16)
+    # sigma = 2, r = 1: exp(-1/8) at the outer taps
+    e2 = np.exp(-0.125)
+    np.testing.assert_allclose(bl.gaussian_taps(2.0, 1), np.array([e2, 1.0, e2]) / (1 + 2 * e2),
+                               rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("sigma", [1.0, 1.5, 2.0, 3.0])
+def test_gaussian_taps_second_moment(sigma):
+    """With the support wide enough that the truncated tail is negligible
+    (r = 8 sigma: tail mass below 1e-14), the taps are the integer samples of
+    exp(-u^2 / (2 sigma^2)), normalised. By Poisson summation their second
+    moment is sigma^2 (1 - 8 pi^2 sigma^2 q / (1 + 2 q)), q = exp(-2 pi^2 sigma^2)
+    (the k = +-1 aliases; the next ones are below 1e-30): a relative 2.1e-7
+    below sigma^2 at sigma = 1, negligible beyond. A sigma^2 / 2 or 2 sigma^2
+    reading of the width fails by a factor of two."""
+    r = int(np.ceil(8 * sigma))
+    g = bl.gaussian_taps(sigma, r)
+    u = np.arange(-r, r + 1)
+    m2 = float(np.sum(u * u * g))
+    q = np.exp(-2.0 * np.pi ** 2 * sigma ** 2)
+    want = sigma ** 2 * (1.0 - 8.0 * np.pi ** 2 * sigma ** 2 * q / (1.0 + 2.0 * q))
+    assert abs(m2 - want) <= 1e-13 * sigma ** 2
+    assert abs(float(np.sum(u * g))) < 1e-15  # centred
+
+
 @pytest.mark.parametrize("sigma,r", [(2.0, 4), (3.0, 7), (1.0, 3), (4.0, 12)])
 @pytest.mark.parametrize("N", [5, 9, 16, 40])
 def test_blur_symmetric_psf(sigma, r, N):
