@@ -304,6 +304,22 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
                      int32_t want_objective, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* fista_step for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same iteration, arguments and results as fista_step, with the
+ * workspace taken from a static device array of the library (64 MiB,
+ * 67108864 bytes, held on every GPU the library runs on until the process
+ * ends) instead of a caller's buffer. Nothing is allocated or freed; the
+ * caller still passes b, the state's x, y, resid and obj. Problems whose
+ * aw_workspace_size(w, b, dtype, batch) exceeds 64 MiB fail with AW_EINVAL
+ * before any device work (2048 x 2048 FP32 at db4, J = 4 needs 38 MiB).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (none of it is read before it is written within a call): calls
+ * that overlap on one GPU, on different streams or threads, race. */
+aw_status fista_step_noalloc(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                             const void* b_obs, double L, double lambda, aw_fista_state* state,
+                             int32_t want_objective, void* stream);
+
 /* The second half of fista_step, from an image-space gradient: with
  * grad = R^*(A y_k - b) (or the gradient of any other smooth term in image
  * space), the coefficient gradient W^* grad (W^dagger grad with

@@ -62,6 +62,8 @@ SIGNATURES = {
     "aw_apply_A_adjoint_fused": [_W, _B, _i32, _i32, _P, _P, _P, _sz, _P],
     "fista_step": [_W, _B, _i32, _i32, _P, _dbl, _dbl, ctypes.POINTER(FistaState), _i32, _P, _sz,
                    _P],
+    "fista_step_noalloc": [_W, _B, _i32, _i32, _P, _dbl, _dbl, ctypes.POINTER(FistaState), _i32,
+                           _P],
     "aw_fista_update": [_W, _i32, _i32, _P, _dbl, _dbl, ctypes.POINTER(FistaState), _i32, _P, _sz,
                         _P],
     "aw_objective": [_W, _B, _i32, _i32, _P, _dbl, _P, _P, _P, _sz, _P],

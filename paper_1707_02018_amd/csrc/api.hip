@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/adjwave.h"
@@ -382,6 +383,118 @@ aw_status wave_common(const aw_wavelet* w, aw_dtype dt, int batch, const void* i
   return need_ws(ws, wsb, l.wave_end);
 }
 
+aw_status op_check(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                   const void* in, const void* out, WavePlan& p, aw::BlurDesc& d,
+                   WsLayout& l) {
+  aw_status st;
+  if ((st = check_dtype(dtype)) != AW_OK) return st;
+  if ((st = make_plan(w, p)) != AW_OK) return st;
+  if ((st = make_blur(b, d)) != AW_OK) return st;
+  if (d.rows != p.rows || d.cols != p.cols)
+    return fail(AW_EINVAL, "wavelet %dx%d and blur %dx%d sizes differ", p.rows, p.cols, d.rows,
+                d.cols);
+  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
+  if (!in || !out) return fail(AW_EINVAL, "NULL data pointer");
+  l = layout_ws(&p, &d, dtype, batch);
+  return AW_OK;
+}
+
+// ------------------------------------------------------------ FISTA step
+// Host-side checks of a FISTA call (no device work): descriptors, sizes,
+// pointers, L, lambda, k, t and the gradient map; fills the plan, the blur
+// and the workspace layout.
+aw_status fista_check(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                      const void* b_obs, double L, double lambda, const aw_fista_state* state,
+                      WavePlan& p, aw::BlurDesc& d, WsLayout& l) {
+  if (!state) return fail(AW_EINVAL, "state is NULL");
+  aw_status st = op_check(w, b, dtype, batch, b_obs, state->resid, p, d, l);
+  if (st != AW_OK) return st;
+  if (!state->x || !state->y) return fail(AW_EINVAL, "state x / y is NULL");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(AW_EINVAL, "L=%g", L);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
+  if (state->k < 1) return fail(AW_EINVAL, "k=%lld (iterations count from 1)", (long long)state->k);
+  if (!(state->t >= 1.0)) return fail(AW_EINVAL, "t=%g (t_1 = 1, increasing)", state->t);
+  if (state->gradient != AW_GRAD_ADJOINT && state->gradient != AW_GRAD_PINV)
+    return fail(AW_EINVAL, "gradient=%d (AW_GRAD_ADJOINT or AW_GRAD_PINV)", (int)state->gradient);
+  return AW_OK;
+}
+
+// The launches of one FISTA iteration on `s` with the workspace at
+// `workspace` (at least l.total bytes), then k and t of the state advanced.
+aw_status fista_enqueue(const WavePlan& p, const aw::BlurDesc& d, const WsLayout& l,
+                        aw_dtype dtype, int32_t batch, const void* b_obs, double L, double lambda,
+                        aw_fista_state* state, int32_t want_objective, void* workspace,
+                        hipStream_t s) {
+  aw_status st;
+  const bool obj = want_objective && state->obj;
+  const int dtype_i = dtype == AW_F64;
+  void* img = wsp(workspace, l.img_off);
+  double* pr = reinterpret_cast<double*>(wsp(workspace, l.pr_off));
+  double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
+  // r = R W y - b
+  if ((st = run_synthesis(p, dtype, batch, state->y, img, workspace, l, 1, s)) != AW_OK) return st;
+  if ((st = hip_check(aw::launch_blur(dtype_i, d, batch, img, state->resid, b_obs,
+                                      obj ? pr : nullptr, s),
+                      "blur launch")) != AW_OK)
+    return st;
+  // g = W^* R^* r
+  if ((st = hip_check(aw::launch_blur_adjoint(dtype_i, d, batch, state->resid, img, s),
+                      "blur_adjoint launch")) != AW_OK)
+    return st;
+  // W^* level by level, each level's gradient coefficients consumed at once
+  // by the prox + momentum update (the gradient never reaches memory)
+  const double t = state->t;
+  const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+  const double beta = (t - 1.0) / tn;
+  // the true adjoint folds with the 1/mult weights of (E^dagger)^*; W^dagger
+  // extends with weight one
+  const int fold_w = state->gradient == AW_GRAD_PINV ? 0 : 1;
+  if ((st = run_analysis_prox(p, dtype, batch, img, state->x, state->y, workspace, l, 1.0 / L,
+                              lambda / L, beta, obj ? pl : nullptr, fold_w, s)) != AW_OK)
+    return st;
+  if (obj) {
+    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, state->obj, 2, 0, s),
+                        "reduce launch")) != AW_OK)
+      return st;
+    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pt, pl, 1.0, state->obj, 2, 1, s),
+                        "reduce launch")) != AW_OK)
+      return st;
+  }
+  state->t = tn;
+  state->k += 1;
+  return ok();
+}
+
+// ------------------------------------------------------- static scratch
+// The workspace of fista_step_noalloc: a file-scope device array, so that
+// call allocates nothing. Every GPU the library runs on holds its own copy
+// (64 MiB) from the time the library's code is loaded on it until the
+// process ends. In host code `scratch` only names the symbol: its device
+// address, per device, comes from hipGetSymbolAddress on the first call on
+// that device and is kept in g_scratch.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {nullptr};
+
+aw_status scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(AW_EUNSUPPORTED, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(AW_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return AW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -613,16 +726,8 @@ aw_status blur_adjoint(const aw_blur* b, aw_dtype dtype, int32_t batch, const vo
 static aw_status op_common(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
                            const void* in, void* out, void* ws, size_t wsb, WavePlan& p,
                            aw::BlurDesc& d, WsLayout& l) {
-  aw_status st;
-  if ((st = check_dtype(dtype)) != AW_OK) return st;
-  if ((st = make_plan(w, p)) != AW_OK) return st;
-  if ((st = make_blur(b, d)) != AW_OK) return st;
-  if (d.rows != p.rows || d.cols != p.cols)
-    return fail(AW_EINVAL, "wavelet %dx%d and blur %dx%d sizes differ", p.rows, p.cols, d.rows,
-                d.cols);
-  if (batch < 1) return fail(AW_EINVAL, "batch=%d", batch);
-  if (!in || !out) return fail(AW_EINVAL, "NULL data pointer");
-  l = layout_ws(&p, &d, dtype, batch);
+  aw_status st = op_check(w, b, dtype, batch, in, out, p, d, l);
+  if (st != AW_OK) return st;
   return need_ws(ws, wsb, l.total);
 }
 
@@ -708,55 +813,30 @@ aw_status fista_step(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int3
   WavePlan p;
   aw::BlurDesc d;
   WsLayout l;
-  if (!state) return fail(AW_EINVAL, "state is NULL");
-  aw_status st = op_common(w, b, dtype, batch, b_obs, state->resid, workspace, workspace_bytes, p,
-                           d, l);
+  aw_status st = fista_check(w, b, dtype, batch, b_obs, L, lambda, state, p, d, l);
   if (st != AW_OK) return st;
-  if (!state->x || !state->y) return fail(AW_EINVAL, "state x / y is NULL");
-  if (!(L > 0.0) || !std::isfinite(L)) return fail(AW_EINVAL, "L=%g", L);
-  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(AW_EINVAL, "lambda=%g", lambda);
-  if (state->k < 1) return fail(AW_EINVAL, "k=%lld (iterations count from 1)", (long long)state->k);
-  if (!(state->t >= 1.0)) return fail(AW_EINVAL, "t=%g (t_1 = 1, increasing)", state->t);
-  if (state->gradient != AW_GRAD_ADJOINT && state->gradient != AW_GRAD_PINV)
-    return fail(AW_EINVAL, "gradient=%d (AW_GRAD_ADJOINT or AW_GRAD_PINV)", (int)state->gradient);
-  const bool obj = want_objective && state->obj;
-  hipStream_t s = (hipStream_t)stream;
-  const int dtype_i = dtype == AW_F64;
-  void* img = wsp(workspace, l.img_off);
-  double* pr = reinterpret_cast<double*>(wsp(workspace, l.pr_off));
-  double* pl = reinterpret_cast<double*>(wsp(workspace, l.pl_off));
-  // r = R W y - b
-  if ((st = run_synthesis(p, dtype, batch, state->y, img, workspace, l, 1, s)) != AW_OK) return st;
-  if ((st = hip_check(aw::launch_blur(dtype_i, d, batch, img, state->resid, b_obs,
-                                      obj ? pr : nullptr, s),
-                      "blur launch")) != AW_OK)
-    return st;
-  // g = W^* R^* r
-  if ((st = hip_check(aw::launch_blur_adjoint(dtype_i, d, batch, state->resid, img, s),
-                      "blur_adjoint launch")) != AW_OK)
-    return st;
-  // W^* level by level, each level's gradient coefficients consumed at once
-  // by the prox + momentum update (the gradient never reaches memory)
-  const double t = state->t;
-  const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-  const double beta = (t - 1.0) / tn;
-  // the true adjoint folds with the 1/mult weights of (E^dagger)^*; W^dagger
-  // extends with weight one
-  const int fold_w = state->gradient == AW_GRAD_PINV ? 0 : 1;
-  if ((st = run_analysis_prox(p, dtype, batch, img, state->x, state->y, workspace, l, 1.0 / L,
-                              lambda / L, beta, obj ? pl : nullptr, fold_w, s)) != AW_OK)
-    return st;
-  if (obj) {
-    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pr, pr, 1.0, state->obj, 2, 0, s),
-                        "reduce launch")) != AW_OK)
-      return st;
-    if ((st = hip_check(aw::launch_reduce_partials(batch, l.n_pt, pl, 1.0, state->obj, 2, 1, s),
-                        "reduce launch")) != AW_OK)
-      return st;
-  }
-  state->t = tn;
-  state->k += 1;
-  return ok();
+  if ((st = need_ws(workspace, workspace_bytes, l.total)) != AW_OK) return st;
+  return fista_enqueue(p, d, l, dtype, batch, b_obs, L, lambda, state, want_objective, workspace,
+                       (hipStream_t)stream);
+}
+
+aw_status fista_step_noalloc(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, int32_t batch,
+                             const void* b_obs, double L, double lambda, aw_fista_state* state,
+                             int32_t want_objective, void* stream) {
+  WavePlan p;
+  aw::BlurDesc d;
+  WsLayout l;
+  aw_status st = fista_check(w, b, dtype, batch, b_obs, L, lambda, state, p, d, l);
+  if (st != AW_OK) return st;
+  if (l.total > kScratchBytes)
+    return fail(AW_EINVAL,
+                "fista_step_noalloc: the problem needs %zu bytes of workspace, more than the "
+                "%zu bytes of the static scratch (call fista_step with a workspace)",
+                l.total, kScratchBytes);
+  void* ws = nullptr;
+  if ((st = scratch_ptr(&ws)) != AW_OK) return st;
+  return fista_enqueue(p, d, l, dtype, batch, b_obs, L, lambda, state, want_objective, ws,
+                       (hipStream_t)stream);
 }
 
 aw_status aw_fista_update(const aw_wavelet* w, aw_dtype dtype, int32_t batch, const void* grad,

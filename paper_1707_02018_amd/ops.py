@@ -393,6 +393,19 @@ def fista_step(state: FistaState, b_obs: torch.Tensor, lam: float, L: float = 1.
     state.k, state.t = int(cs.k), float(cs.t)
 
 
+def fista_step_noalloc(state: FistaState, b_obs: torch.Tensor, lam: float, L: float = 1.0,
+                       want_objective: bool = False) -> None:
+    """fista_step with the library's static device scratch as its workspace
+    (no allocation; problems up to 64 MiB of workspace). Calls that overlap
+    on one GPU share that scratch and race."""
+    cs = state.c_state()
+    check("fista_step_noalloc",
+          load().fista_step_noalloc(state.w.c, state.b.c, _dtype_code(b_obs), state.batch,
+                                    _ptr(_dev(b_obs)), float(L), float(lam), ctypes.byref(cs),
+                                    int(bool(want_objective)), _stream(b_obs)))
+    state.k, state.t = int(cs.k), float(cs.t)
+
+
 def fista_update(state: FistaState, grad: torch.Tensor, lam: float, L: float = 1.0,
                  want_l1: bool = False) -> None:
     """The update half of a FISTA iteration from an image-space gradient

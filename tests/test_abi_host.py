@@ -129,6 +129,21 @@ def test_entry_points_validate_before_launch(lib):
     st.k = 1
     assert lib.fista_step(W, B, 0, 1, dummy, 0.0, 2e-5, ctypes.byref(st), 0, ws, 1 << 30,
                           None) == _lib.EINVAL  # L = 0
+    assert lib.fista_step_noalloc(W, B, 0, 1, dummy, 0.0, 2e-5, ctypes.byref(st), 0,
+                                  None) == _lib.EINVAL  # L = 0
+    assert lib.fista_step_noalloc(W, B, 0, 1, dummy, 1.0, 2e-5, None, 0,
+                                  None) == _lib.EINVAL  # no state
+    # a problem whose workspace exceeds the 64 MiB static scratch
+    wb, bb = _lib.Wavelet(), _lib.Blur()
+    ctypes.memmove(ctypes.byref(wb), ctypes.byref(w), ctypes.sizeof(w))
+    wb.rows = wb.cols = 4096
+    bb.rows = bb.cols = 4096
+    bb.radius = 4
+    for i, v in enumerate(obl.gaussian_taps(2.0, 4)):
+        bb.taps[i] = v
+    assert lib.fista_step_noalloc(ctypes.byref(wb), ctypes.byref(bb), 0, 1, dummy, 1.0, 2e-5,
+                                  ctypes.byref(st), 0, None) == _lib.EINVAL
+    assert b"static scratch" in lib.aw_last_error()
     S = ctypes.byref(st)
     assert lib.aw_fista_update(W, 0, 1, dummy, 1.0, 2e-5, None, 0, ws, 1 << 30,
                                None) == _lib.EINVAL  # no state
