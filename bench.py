@@ -9,10 +9,22 @@ application plus the proximal/momentum update) on a 2048 x 2048 FP32 image:
 rectangles-plus-gradient image with N(0, 1e-3^2) noise. The headline value is
 image Mpix per second through A and A^* (one of each per step).
 
+The roofline reported is the whole iteration's: its algorithmic bytes
+(4 (5 ncoef + 3 npix)) over the step time from HIP events on the launching
+stream, with the Infinity Cache warm (the 2048^2 working set stays in it)
+and, beside it, the same step streaming from HBM (12 problems in rotation).
+
 Also reported: Mpix/s of W, W^*, R, R^*, A, A^* alone (graph-replayed, HIP
-events), iterations to 1e-4 relative objective and the time to reach it, the
-dominant kernel against the HBM roofline, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+events, hot and streaming from HBM), standalone single-kernel
+microbenchmarks against 8 TB/s, the time to reach a 1e-4 relative objective
+measured end to end, the extra workloads (uneven batch, autograd, the
+convolution pair, the learned warm start, R through the DCT, the adjoint
+study, blind channel estimation), and the FP64 CPU oracle timed on bounded
+samples of the same workloads (host CPU model and core count recorded).
+
+Profiling modes: --only-step K runs K FISTA steps only; --trace-summary and
+--pmc-summary turn rocprofv3 output of such a run into the per-launch table
+and the step traffic record kept under profiles/.
 """
 from __future__ import annotations
 
@@ -33,77 +45,130 @@ HBM_PEAK_GBS = 8000.0
 COPY_REF_BYTES = 256 << 20  # read (and again written) by the --copy-reference kernel
 
 
-# Kernels whose HBM traffic the roofline reports: op name -> (kernel name prefix,
-# grid size at 2048^2 db4 J=4, source file whose hash the record carries).
-PMC_KERNELS = {
-    "W_level1": ("void aw::synth_level_kernel<float, 8, 1, 0>", 524288, "wavelet.hip"),
-    "W*_level1": ("void aw::ana_level_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
-    "R": ("void aw::blur_tile_kernel<float, 7, false, 0>", 524288, "blur.hip"),
-    "R*": ("void aw::blur_tile_kernel<float, 7, true, 0>", 524288, "blur.hip"),
-    "W*prox_level1": ("void aw::ana_prox_kernel<float, 8, 1, 0>", 557568, "wavelet.hip"),
-}
+# The eight launches of one FISTA step at 2048^2 (db4, J = 4, sym), in
+# launch order: what each reads and writes (FP32 values), from the layout
+# sizes K_j (rows = cols): the kernel-level algorithmic bytes.
+STEP_KERNELS = ["synth_chain (W levels 4..2)", "synth_level (W level 1)", "blur (R y - b)",
+                "blur (R^*)", "ana_prox level 1 (W^* + update)", "ana_prox level 2",
+                "ana_prox level 3", "ana_prox level 4 (+ a_4)"]
+STEP_SOURCES = ["wavelet.hip", "blur.hip", "api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fista2048_sym.md")
 
 
-def source_hash(name: str) -> str:
-    """Hash of a kernel source file and every internal header it can include."""
+def step_kernel_bytes(sr, sc, npix: int, ncoef: int) -> list:
+    """Algorithmic bytes of each step launch: every input read once, every
+    output written once (intermediates between launches included)."""
+    k = [sr[j] * sc[j] for j in range(len(sr))]
+    J = len(sr) - 1
+    coarse = ncoef - 3 * k[1]  # y's coefficients of levels 2..J and a_J
+    out = [coarse + k[1],                    # chain: y levels >= 2 in, a_1 out
+           4 * k[1] + npix,                  # level 1: a_1 and y's three bands in, image out
+           3 * npix,                         # R y - b: image, b in, r out
+           2 * npix,                         # R^*: r in, g out
+           npix + 12 * k[1] + k[1]]          # level-1 analysis: g in; x, y of 3 bands in+out; a_1 out
+    for j in range(2, J + 1):
+        bands = 4 if j == J else 3
+        out.append(k[j - 1] + 4 * bands * k[j] + (0 if j == J else k[j]))
+    return [4 * v for v in out]
+
+
+def source_hash(names) -> str:
+    """Hash of kernel sources and every internal header they can include."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_02018_amd", "csrc")
     h = hashlib.sha256()
-    for f in [name] + sorted(x for x in os.listdir(csrc) if x.endswith(".hpp")):
+    for f in list(names) + sorted(x for x in os.listdir(csrc) if x.endswith(".hpp")):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def pmc_summary(fetch_csv: str, write_csv: str) -> None:
-    """Per-launch HBM bytes of the roofline kernels: counter averages scaled by
-    what the same counters read for the --copy-reference kernel."""
+def _step_dispatches(rows, name_key, steps: int):
+    """Library dispatches of a --only-step run in dispatch order, the first
+    (the blur that forms b) dropped, grouped per step: steps x 8 rows."""
+    aw = sorted((r for r in rows if "aw::" in r[name_key]), key=lambda r: int(r["Dispatch_Id"]))
+    aw = aw[1:]
+    n = len(STEP_KERNELS)
+    if len(aw) != steps * n:
+        raise SystemExit(f"expected {steps * n} step dispatches, found {len(aw)}")
+    return [aw[i * n:(i + 1) * n] for i in range(steps)]
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, steps: int) -> None:
+    """HBM bytes per FISTA step from two rocprofv3 --pmc passes (FETCH_SIZE,
+    then WRITE_SIZE) of `bench.py --only-step STEPS --copy-reference`: the
+    counters of each step launch, scaled by what the same counters read for
+    the known-size copy kernel."""
     import csv
 
     def load(path, counter):
-        out = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == counter:
-                out.setdefault((r["Kernel_Name"], int(r["Grid_Size"])), []).append(
-                    float(r["Counter_Value"]))
-        return out
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        return rows
 
-    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
-
-    def avg(tab, prefix, grid):
-        v = [x for (k, g), xs in tab.items() if k.startswith(prefix) and g == grid for x in xs]
-        return sum(v) / len(v), len(v)
-
-    ref = ("void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, "
-           "float, float, at::native::binary_internal::MulFunctor<float> >", COPY_REF_BYTES // 16)
-    kib = COPY_REF_BYTES / 1024
-    ff = kib / avg(f, *ref)[0]
-    wf = kib / avg(w, *ref)[0]
-    for op, (kname, grid, src) in PMC_KERNELS.items():
-        fa, n = avg(f, kname, grid)
-        wa, _ = avg(w, kname, grid)
-        rec = {"op": op, "kernel": kname[5:], "grid": grid, "dispatches": n,
-               "fetch_kib": round(fa, 1), "write_kib": round(wa, 1),
-               "fetch_factor": round(ff, 5), "write_factor": round(wf, 5),
-               "bytes_per_launch": int(1024 * (fa * ff + wa * wf)),
-               "source": src, "source_sha": source_hash(src)}
-        print("traffic-record: " + json.dumps(rec))
+    out = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = load(path, counter)
+        ref = [float(r["Counter_Value"]) for r in rows
+               if "elementwise" in r["Kernel_Name"] and int(r["Grid_Size"]) == COPY_REF_BYTES // 16]
+        factor = (COPY_REF_BYTES / 1024) / (sum(ref) / len(ref))
+        groups = _step_dispatches(rows, "Kernel_Name", steps)
+        per = [sum(float(g[i]["Counter_Value"]) for g in groups) / steps
+               for i in range(len(STEP_KERNELS))]
+        out[counter] = (factor, per)
+    ff, fk = out["FETCH_SIZE"]
+    wf, wk = out["WRITE_SIZE"]
+    per_kernel = [int(1024 * (f * ff + w * wf)) for f, w in zip(fk, wk)]
+    rec = {"unit": "fista_step_2048_db4_J4_sym", "steps": steps,
+           "fetch_factor": round(ff, 5), "write_factor": round(wf, 5),
+           "fetch_kib": [round(v, 1) for v in fk], "write_kib": [round(v, 1) for v in wk],
+           "bytes_per_kernel": per_kernel, "bytes_per_step": sum(per_kernel),
+           "sources": STEP_SOURCES, "source_sha": source_hash(STEP_SOURCES)}
+    print("step-traffic-record: " + json.dumps(rec))
 
 
-def traffic_for(op: str):
-    """HBM bytes per launch of ``op`` from the committed counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
+def step_traffic():
+    """HBM bytes per FISTA step from the committed counter summary, or None
+    when there is none or a kernel source changed since it was taken."""
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
         return None
     for ln in lines:
-        if ln.startswith("traffic-record: "):
-            rec = json.loads(ln[len("traffic-record: "):])
-            if rec["op"] == op and rec["source_sha"] == source_hash(rec["source"]):
-                return rec["bytes_per_launch"]
+        if ln.startswith("step-traffic-record: "):
+            rec = json.loads(ln[len("step-traffic-record: "):])
+            if rec["source_sha"] == source_hash(rec["sources"]):
+                return rec
     return None
+
+
+def trace_summary(trace_csv: str, steps: int, N: int = 2048) -> None:
+    """Per-launch table of the FISTA step from a rocprofv3 kernel trace of
+    `bench.py --only-step STEPS`: average duration of each of the eight
+    launches and its kernel-level algorithmic bytes against 8 TB/s."""
+    import csv
+
+    from paper_1707_02018_amd import ops
+    rows = list(csv.DictReader(open(trace_csv)))
+    groups = _step_dispatches(rows, "Kernel_Name", steps)
+    w = ops.WaveletSpec(N, N, 4, taps=8, bc="sym")
+    _, sr, sc = w.layout()
+    kb = step_kernel_bytes(sr, sc, N * N, w.ncoef)
+    total_us = 0.0
+    print("| # | launch | kernel | workgroups | avg us | bytes (MB) | TB/s | of 8 TB/s |")
+    print("|---|---|---|---|---|---|---|---|")
+    for i, name in enumerate(STEP_KERNELS):
+        d = [(int(g[i]["End_Timestamp"]) - int(g[i]["Start_Timestamp"])) / 1e3 for g in groups]
+        us = sum(d) / len(d)
+        total_us += us
+        r0 = groups[0][i]
+        wg = (int(r0["Grid_Size_X"]) // int(r0["Workgroup_Size_X"])) * int(r0["Grid_Size_Y"])
+        kern = r0["Kernel_Name"].split("(")[0].replace("void ", "")
+        print(f"| {i + 1} | {name} | `{kern}` | {wg} | {us:.2f} | {kb[i] / 1e6:.2f} | "
+              f"{kb[i] / us / 1e6:.2f} | {100 * kb[i] / us / 1e6 / 8:.1f} % |")
+    alg = 4 * (5 * w.ncoef + 3 * N * N)
+    print(f"\nSum of the launches: {total_us:.2f} us per step; the iteration's algorithmic "
+          f"bytes (4 (5 ncoef + 3 npix) = {alg / 1e6:.1f} MB) over it: "
+          f"{alg / total_us / 1e6:.2f} TB/s, {100 * alg / total_us / 1e6 / 8:.1f} % of 8 TB/s.")
 
 
 def log(msg: str) -> None:
@@ -127,9 +192,16 @@ def parse():
     ap.add_argument("--only-conv", action="store_true",
                     help="run only the convolution-pair section and print its JSON (for profiling)")
     ap.add_argument("--warm-images", type=int, default=16)
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="print traffic records from two rocprofv3 --pmc counter CSVs "
-                         "(FETCH_SIZE, WRITE_SIZE) of a --copy-reference run, then exit")
+    ap.add_argument("--only-step", type=int, default=0, metavar="STEPS",
+                    help="run only STEPS FISTA steps at the bench size (for profiler passes)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "STEPS"),
+                    help="print the step traffic record from two rocprofv3 --pmc counter CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE) of --only-step STEPS --copy-reference, then exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_CSV", "STEPS"),
+                    help="print the per-launch step table from a rocprofv3 kernel trace of "
+                         "--only-step STEPS, then exit")
+    ap.add_argument("--cpu-leg", action="store_true",
+                    help="(internal) run the oracle legs of the CPU baseline and print JSON")
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB copy kernel (x * 1 into y) three times, "
                          "the known-size reference for hardware byte counters")
@@ -361,6 +433,81 @@ def bench_cold(torch, ops, lib, w, w1, bsp, lam: float, stream, nsets: int = 12)
                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
+def bench_step_cold(torch, ops, w, bsp, b, lam: float, nsets: int = 12, rounds: int = 4) -> dict:
+    """The FISTA step over `nsets` independent problems stepped in rotation,
+    each with its own b, x, y, residual and workspace (about 107 MB per
+    problem at 2048^2, more than the 256 MB Infinity Cache in all), so every
+    step streams its operands from HBM; HIP events on the launching stream."""
+    states = []
+    for _ in range(nsets):
+        bi = b.clone()
+        st = ops.FistaState(w, bsp, bi)
+        for _ in range(3):
+            ops.fista_step(st, bi, lam)
+        states.append((st, bi))
+    torch.cuda.synchronize()
+    per_set = (2 * w.ncoef * 4 + 2 * b.numel() * 4 + states[0][0].ws_n)
+    cur = torch.cuda.current_stream(b.device)
+    for st, bi in states:
+        ops.fista_step(st, bi, lam)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    for _ in range(rounds):
+        for st, bi in states:
+            ops.fista_step(st, bi, lam)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / (rounds * nsets)
+    del states
+    torch.cuda.empty_cache()
+    return {"us_per_step": round(us, 3), "sets": nsets,
+            "protocol": f"{nsets} independent 2048^2 problems (b, x, y, residual and workspace "
+                        f"each; {nsets * per_set / 1e9:.2f} GB in all) stepped in rotation, "
+                        f"{rounds} rounds, HIP events on the launching stream"}
+
+
+def bench_time_to_target(torch, ops, w, bsp, b, lam: float, ms_per_step: float,
+                         total: int = 20000, every: int = 20, check: int = 10) -> dict:
+    """Plain FISTA from zero to a relative objective of 1e-4, measured end to
+    end. F* is the lowest exact objective over `total` plain iterations
+    (checked every `every`). A fresh run from zero then evaluates the exact
+    objective every `check` iterations and stops at the first check at or
+    below 1e-4; its wall time, objective passes and reads included, is the
+    time to target."""
+    dev = b.device
+    st2 = ops.FistaState(w, bsp, b)
+    obj = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    Fs = []
+    for k in range(1, total + 1):
+        ops.fista_step(st2, b, lam)
+        if k % every == 0:
+            ops.objective(w, bsp, b, st2.x, lam, out=obj)
+            Fs.append((k, obj[0, 2].item()))
+    F_star = min(F for _, F in Fs)
+    del st2
+    st3 = ops.FistaState(w, bsp, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k, hit = 0, None
+    while k < total:
+        for _ in range(check):
+            ops.fista_step(st3, b, lam)
+        k += check
+        ops.objective(w, bsp, b, st3.x, lam, out=obj)
+        if (obj[0, 2].item() - F_star) / F_star <= 1e-4:
+            hit = k
+            break
+    dt = time.perf_counter() - t0
+    return {"F_star": F_star, "F_star_from": f"min exact F over {total} plain iterations "
+                                               f"(every {every})",
+            "iters_to_1e-4": hit, "checked_every": check,
+            "time_to_1e-4_ms": round(1e3 * dt, 3) if hit else None,
+            "measured": f"end to end: wall time from x = 0 to the first check at or below 1e-4, "
+                        f"one exact objective pass and one 8-byte read every {check} "
+                        f"iterations included",
+            "steps_only_ms": round(hit * ms_per_step, 3) if hit else None}
+
+
 def bench_modes(torch, ops, lib, bsp, b, lam: float, modes, steps: int = 100) -> dict:
     """The same 2048^2 workload with the other boundary modes: FISTA step
     time and Mpix/s, and A, A^* per application."""
@@ -467,55 +614,152 @@ def bench_blind() -> dict:
             for sd in (0, 1)}
 
 
+def _pool_fista(task):
+    """One worker of the CPU pool legs: `iters` oracle FISTA iterations on
+    one image (single-threaded NumPy); returns its pixel count."""
+    rows, cols, levels, taps, sigma, radius, seed, iters = task
+    from oracle import blur as bl, filters as fl, fista as fi
+    from workloads import gen_image, gen_noise, rng_for
+    rng = rng_for(*seed)
+    img = gen_image(rng, rows, cols)
+    psf = bl.gaussian_taps(sigma, radius)
+    b = bl.R(img, psf) + gen_noise(rng, img.shape)
+    prob = fi.Problem(rows, cols, fl.by_taps(taps), "sym", levels, psf)
+    fi.fista(prob, b, 2e-5, iters)
+    return rows * cols * iters
+
+
+def cpu_leg(size: int, bc: str, iters: int = 2) -> dict:
+    """The FP64 NumPy oracle on this host (never in the GPU process): bounded
+    samples of the benchmark's workloads. Single-threaded legs run with one
+    BLAS thread; the pool legs run one single-threaded worker per core, up
+    to 16 (one GPU's share of the host)."""
+    import multiprocessing as mp
+    import platform
+
+    import numpy as np
+
+    from oracle import blur as bl, conv as cv, filters as fl, fista as fi, wavelet as wv
+    from workloads import gen_batched_config, gen_conv_pair, gen_image, gen_noise, rng_for
+    out = {}
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        model = platform.processor()
+    ncpu = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = ncpu
+    out["host"] = {"cpu_model": model, "nproc": ncpu, "affinity_cpus": avail}
+    # 1. the headline step at full size
+    rng = rng_for(2, 0)
+    img = gen_image(rng, size, size)
+    psf = bl.gaussian_taps(3.0, 7)
+    b = bl.R(img, psf) + gen_noise(rng, img.shape)
+    prob = fi.Problem(size, size, fl.by_taps(8), bc, 4, psf)
+    t0 = time.perf_counter()
+    fi.fista(prob, b, 2e-5, iters)
+    out["sec_per_iter"] = (time.perf_counter() - t0) / iters
+    h = fl.by_taps(8)
+    x = np.random.default_rng(0).standard_normal(prob.ncoef) * 1e-2
+    ops_ = {"W": lambda: wv.W(x, h, bc, 4, size, size), "W*": lambda: wv.W_adj(img, h, bc, 4),
+            "R": lambda: bl.R(img, psf), "R*": lambda: bl.R_adj(img, psf),
+            "A": lambda: prob.A(x), "A*": lambda: prob.A_adj(img)}
+    op_s = {}
+    for name, fn in ops_.items():
+        t1 = time.perf_counter()
+        fn()
+        op_s[name] = time.perf_counter() - t1
+    out["op_s"] = op_s
+    # 2. the small configuration: 200 iterations at 256^2, db4 J = 3, 9x9 PSF
+    rng = rng_for(1, 0)
+    img1 = gen_image(rng, 256, 256)
+    psf1 = bl.gaussian_taps(2.0, 4)
+    b1 = bl.R(img1, psf1) + gen_noise(rng, img1.shape)
+    prob1 = fi.Problem(256, 256, fl.by_taps(8), "sym", 3, psf1)
+    t0 = time.perf_counter()
+    fi.fista(prob1, b1, 2e-5, 200)
+    out["small_200_iters_s"] = time.perf_counter() - t0
+    # 3. the convolution pair (K = 128, N = 65536), 64 of the 256 pairs
+    rng = rng_for(4, 0)
+    pairs = [gen_conv_pair(rng, 128, 65536) for _ in range(64)]
+    t0 = time.perf_counter()
+    for hh, ss in pairs:
+        cv.conv_adjoint_pair(hh[None], ss[None], None)
+    dt = time.perf_counter() - t0
+    out["conv_pairs"] = {"pairs": 64, "s": dt,
+                         "GFLOPs": 2.0 * 64 * 3 * 128 * 65536 / dt / 1e9}
+    # 4. pool legs: the 16 smallest images of the uneven batch (one iteration
+    #    each), and 512^2 warm-start-sized problems (20 iterations each)
+    workers = max(1, min(avail, 16))
+    cfg = gen_batched_config(rng_for(3, 0), 64)
+    small = sorted(range(64), key=lambda i: cfg[i]["rows"] * cfg[i]["cols"])[:16]
+    tasks3 = [(cfg[i]["rows"], cfg[i]["cols"], cfg[i]["levels"], cfg[i]["taps"], cfg[i]["sigma"],
+               cfg[i]["radius"], (3, 1000 + i), 1) for i in small]
+    tasks5 = [(512, 512, 4, 8, 2.0, 6, (50, i), 20) for i in range(workers)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for key, tasks in (("pool_uneven_batch", tasks3), ("pool_512", tasks5)):
+            t0 = time.perf_counter()
+            pix = sum(pool.map(_pool_fista, tasks, chunksize=1))
+            dt = time.perf_counter() - t0
+            out[key] = {"workers": workers, "images": len(tasks), "s": dt,
+                        "mpix_iter_per_s": pix / dt / 1e6}
+    return out
+
+
 def cpu_baseline(size: int, bc: str, iters: int = 2) -> dict:
-    """The FP64 NumPy oracle timed on this host (separate process), a bounded
-    sample of the same workload: `iters` FISTA iterations at full size."""
-    code = f"""
-import sys, time, json
-sys.path.insert(0, {ROOT!r})
-import numpy as np
-from oracle import blur as bl, filters as fl, fista as fi
-from workloads import gen_image, gen_noise, rng_for
-rng = rng_for(2, 0)
-img = gen_image(rng, {size}, {size})
-psf = bl.gaussian_taps(3.0, 7)
-b = bl.R(img, psf) + gen_noise(rng, img.shape)
-prob = fi.Problem({size}, {size}, fl.by_taps(8), {bc!r}, 4, psf)
-t0 = time.perf_counter()
-fi.fista(prob, b, 2e-5, {iters})
-dt = time.perf_counter() - t0
-from oracle import wavelet as wv
-h = fl.by_taps(8)
-x = np.random.default_rng(0).standard_normal(prob.ncoef) * 1e-2
-ops = {{"W": lambda: wv.W(x, h, {bc!r}, 4, {size}, {size}),
-       "W*": lambda: wv.W_adj(img, h, {bc!r}, 4),
-       "R": lambda: bl.R(img, psf), "R*": lambda: bl.R_adj(img, psf),
-       "A": lambda: prob.A(x), "A*": lambda: prob.A_adj(img)}}
-op_s = {{}}
-for name, fn in ops.items():
-    t1 = time.perf_counter()
-    fn()
-    op_s[name] = time.perf_counter() - t1
-print(json.dumps({{"sec_per_iter": dt / {iters}, "op_s": op_s}}))
-"""
+    """The FP64 NumPy oracle timed on this host in a separate process, on
+    bounded samples of the same workloads (about half a minute of CPU work)."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", "--size",
+                          str(size), "--bc", bc], capture_output=True, text=True, env=env,
+                         timeout=900)
     if out.returncode != 0:
         return {"error": out.stderr[-500:]}
     res = json.loads(out.stdout.strip().splitlines()[-1])
     spi = res["sec_per_iter"]
+    pool3, pool5 = res["pool_uneven_batch"], res["pool_512"]
     return {"value": size * size / spi / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} FISTA iterations (one A and one A* each) at {size}x{size}, "
-                      f"FP64 NumPy, single thread; {spi:.2f} s/iteration",
+                      f"FP64 NumPy, one thread; {spi:.2f} s/iteration",
+            "host": res["host"],
             "ops_mpix_s": {k: round(size * size / v / 1e6, 3) for k, v in res["op_s"].items()},
-            "ops_sample": "one application each of W, W*, R, R*, A, A* at the same size"}
+            "ops_sample": "one application each of W, W*, R, R*, A, A* at the same size, one thread",
+            "small_config_200_iters": {"s": round(res["small_200_iters_s"], 3), "cores": 1,
+                                       "sample": "256x256 FP64, db4 J=3 sym, 9x9 PSF sigma 2, "
+                                                 "200 FISTA iterations from zero"},
+            "conv_adjoint_pair": {"GFLOPs": round(res["conv_pairs"]["GFLOPs"], 3), "cores": 1,
+                                  "sample": "64 of the 256 pairs (K=128, N=65536): h*s and the "
+                                            "two valid correlations, np.convolve FP64"},
+            "uneven_batch_pool": {"mpix_iter_per_s": round(pool3["mpix_iter_per_s"], 3),
+                                  "cores": pool3["workers"],
+                                  "sample": "the 16 smallest images of the 64-image uneven batch, "
+                                            "one FISTA iteration each, one single-threaded worker "
+                                            f"per core ({pool3['workers']} workers), "
+                                            f"{pool3['s']:.1f} s"},
+            "warm_start_size_pool": {"mpix_iter_per_s": round(pool5["mpix_iter_per_s"], 3),
+                                     "cores": pool5["workers"],
+                                     "sample": f"{pool5['images']} 512x512 problems (db4 J=4 sym, "
+                                               "13x13 PSF), 20 FISTA iterations each, one worker "
+                                               f"per core, {pool5['s']:.1f} s"}}
 
 
 def main():
     args = parse()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], int(args.pmc_summary[2]))
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], int(args.trace_summary[1]), args.size)
+        return
+    if args.cpu_leg:
+        print(json.dumps(cpu_leg(args.size, args.bc)))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -553,18 +797,30 @@ def main():
     noise = torch.tensor(gen_noise(rng, (N, N)), dtype=torch.float32, device=dev)
     b = ops.blur(bsp, img) + noise
     torch.cuda.synchronize()
+    if args.only_step:
+        st = ops.FistaState(w, bsp, b)
+        for _ in range(args.only_step):
+            ops.fista_step(st, b, lam)
+        torch.cuda.synchronize()
+        print(json.dumps({"only_step": args.only_step}))
+        return
 
     # ---------------------------------------------------------- headline
     st = ops.FistaState(w, bsp, b)
     for _ in range(args.warmup):
         ops.fista_step(st, b, lam)
     torch.cuda.synchronize()
+    cur = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record(cur)
     for _ in range(args.steps):
         ops.fista_step(st, b, lam)
+    ev1.record(cur)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
+    ms_per_step_events = ev0.elapsed_time(ev1) / args.steps
     value = npix * args.steps / dt / 1e6
 
     # ------------------------------------------- per-operator graph timings
@@ -619,49 +875,50 @@ def main():
     # cache-resident
     cold = bench_cold(torch, ops, lib, w, w1, bsp, lam, stream)
 
-    # dominant single-kernel operator of the step that bench.py can time alone:
-    # the level-1 synthesis or analysis, R, R^*, or the level-1 update (the
-    # image in; x_{k-1}, y_k read and x_k, y_{k+1} written for the four bands)
+    # the reported roofline: the whole FISTA iteration against its
+    # algorithmic bytes (y and b read, r written for A y - b; r, y and
+    # x_{k-1} read, x_k and y_{k+1} written for A^* and the update), step time
+    # from HIP events on the launching stream over the timed region
+    step_bytes = 4 * (5 * ncoef + 3 * npix)
+    step_gbs = step_bytes / (ms_per_step_events * 1e-3) / 1e9
+    trec = step_traffic()
+    roofline = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                "traffic": trec["bytes_per_step"] if trec else None,
+                "kernel": "fista_step: one FISTA iteration (8 launches: W levels 4..2, W level 1, "
+                          "R y - b, R^*, W^* + update levels 1..4)",
+                "algorithmic_bytes": step_bytes, "avg_us": round(1e3 * ms_per_step_events, 3),
+                "cache": "hot: the 2048^2 working set stays in the 256 MB Infinity Cache between "
+                         "iterations"}
+    # the whole step streaming from HBM: 12 independent problems in rotation
+    step_cold = bench_step_cold(torch, ops, w, bsp, b, lam)
+    roofline["cold_hbm"] = {"avg_us": step_cold["us_per_step"],
+                            "achieved": round(step_bytes / (step_cold["us_per_step"] * 1e-6) / 1e9,
+                                              1),
+                            "frac": round(step_bytes / (step_cold["us_per_step"] * 1e-6) / 1e9 /
+                                          HBM_PEAK_GBS, 4),
+                            "protocol": step_cold["protocol"]}
+    # standalone single-kernel operators (microbenchmarks, not the step's own
+    # launches): hot replays and the same streaming from HBM
     _, sr, sc = w.layout()
     k1 = sr[1] * sc[1]
     alg_bytes = {"W*_level1": 4 * (npix + 4 * k1), "W_level1": 4 * (npix + 4 * k1),
                  "R": 8 * npix, "R*": 8 * npix, "W*prox_level1": 4 * (npix + 16 * k1)}
-    dom = max(alg_bytes, key=lambda k: op_us[k])
-    achieved = alg_bytes[dom] / (op_us[dom] * 1e-6) / 1e9
-    kernel_names = {"W*_level1": "ana_level_kernel<float,8,SYM,0>",
-                    "W_level1": "synth_level_kernel<float,8,SYM,0>",
-                    "R": "blur_tile_kernel<float,7,fwd,0>", "R*": "blur_tile_kernel<float,7,adj,0>",
-                    "W*prox_level1": "ana_prox_kernel<float,8,SYM,0>"}
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom),
-                "kernel": kernel_names[dom], "op": dom, "algorithmic_bytes": alg_bytes[dom],
-                "avg_us": round(op_us[dom], 3)}
-    # the whole iteration against its algorithmic bytes: y and b read, r
-    # written (A y - b); r, y and x_{k-1} read, x_k and y_{k+1} written (A^*
-    # and the update)
-    step_bytes = 4 * (5 * ncoef + 3 * npix)
-    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
-    step_roofline = {"algorithmic_bytes": step_bytes, "achieved": round(step_gbs, 1),
-                     "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    standalone = {}
+    for op, nb in alg_bytes.items():
+        rec_ = {"algorithmic_bytes": nb, "hot_us": round(op_us[op], 3),
+                "hot_frac": round(nb / (op_us[op] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        if op in cold["ops_us"]:
+            cu = cold["ops_us"][op]
+            rec_.update({"cold_us": cu, "cold_frac": round(nb / (cu * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                                           4)})
+        standalone[op] = rec_
 
     # ------------------------------------------------ time to 1e-4 (plain)
     target = None
     if not args.no_target:
         log("time to 1e-4 (2048^2, plain)")
-        st2 = ops.FistaState(w, bsp, b)
-        obj = torch.empty(1, 3, dtype=torch.float64, device=dev)
-        Fs = []
-        every, total = 20, 20000
-        for k in range(1, total + 1):
-            ops.fista_step(st2, b, lam)
-            if k % every == 0:
-                ops.objective(w, bsp, b, st2.x, lam, out=obj)
-                Fs.append((k, obj[0, 2].item()))
-        F_star = min(F for _, F in Fs)
-        k_hit = next((k for k, F in Fs if (F - F_star) / F_star <= 1e-4), None)
-        target = {"F_star": F_star, "F_star_from": f"min F over {total} plain iterations",
-                  "iters_to_1e-4": k_hit, "checked_every": every,
-                  "time_to_1e-4_ms": round(k_hit * ms_per_step, 3) if k_hit else None}
+        target = bench_time_to_target(torch, ops, w, bsp, b, lam, ms_per_step)
 
     extras = {}
     if not args.no_extras:
@@ -701,12 +958,13 @@ def main():
                    "psf_radius": 7, "psf_sigma": 3.0, "lambda": lam, "ncoef": ncoef,
                    "batch": 1},
         "fista_iters_per_s": round(1e3 / ms_per_step, 1),
+        "ms_per_step_hip_events": round(ms_per_step_events, 4),
         "ops_us": {k: round(v, 3) for k, v in op_us.items()},
         "ops_mpix_s": ops_mpix,
         "ops_cache": "hot: inputs resident in the 256 MB Infinity Cache between replays",
         "ops_cold_hbm": cold,
         "roofline": roofline,
-        "step_roofline": step_roofline,
+        "standalone_kernels": standalone,
         "time_to_target": target,
         **extras,
         "cpu_baseline": cpu,
