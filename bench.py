@@ -310,8 +310,10 @@ def bench_conv(torch, ops) -> dict:
 def bench_warm(torch, ops, n_images: int) -> dict:
     """Learned warm start against FISTA from zero on fresh 512^2 images
     (db4, J = 4, sym, PSF sigma ~ U[1, 3], lambda = 2e-5) with the committed
-    checkpoint: iterations to the 1e-4 relative objective per image and the
-    batch wall time until its slowest image gets there."""
+    checkpoint, in one batched plan with converged images dropping out:
+    iterations to the 1e-4 relative objective per image (capped at 40,000)
+    and the batch wall time until its last image gets there (warm: the CNN
+    and the start included)."""
     from paper_1707_02018_amd import learned
 
     ckpt = os.path.join(ROOT, "paper_1707_02018_amd", "weights", "warmstart_db4_J4_512.npz")
@@ -329,8 +331,8 @@ def bench_warm(torch, ops, n_images: int) -> dict:
         learned.warm_start(net, w, b, 2e-5)
     torch.cuda.synchronize()
     cnn_ms = 1e3 * (time.perf_counter() - t0) / 10
-    res = learned.evaluate(net, w, n_images, 2e-5, seed=72, device=dev, star_iters=16000,
-                           max_iters=12000, every=40, chunk=n_images)
+    res = learned.evaluate(net, w, n_images, 2e-5, seed=72, device=dev, star_iters=60000,
+                           max_iters=40000, every=100, chunk=n_images)
     s = learned.summarize(res)
     s["warm_start_map_ms"] = round(cnn_ms, 3)
     s["cnn_gflop_per_image"] = round(2 * 37440 * 512 * 512 / 1e9, 2)

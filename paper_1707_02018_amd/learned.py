@@ -275,54 +275,86 @@ def choose_starts(w, blurs, b, x0: torch.Tensor, lam: float):
     return x0, ok
 
 
+def timed_run(bf: BatchedFista, w, blurs, b, lam: float, F_star: np.ndarray, tol: float,
+              every: int, max_iters: int, net: WarmStartCNN | None = None, k0: int = 1):
+    """FISTA on the batch until every problem reaches (F(x_k) - F*) / F* <= tol,
+    converged problems dropping out: every `every` iterations the exact
+    objective of each active problem is evaluated, and a problem at or below
+    tol is frozen (its tiles skip from then on). With `net`, the start is the
+    network's (fallback rule applied) and the momentum sequence starts at
+    k0; the start is computed inside the timed region. Returns the first
+    checked k of each problem (-1: not within max_iters), the wall time, and
+    the fallback flags."""
+    n = len(blurs)
+    dev = b.device
+    obj = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    X = bf.X.view(n, -1)
+    bf.reset()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    ok = None
+    if net is not None:
+        x0, ok = choose_starts(w, blurs, b, warm_start(net, w, b, lam), lam)
+        X.copy_(x0)
+        bf.Y.copy_(bf.X)
+        if k0 > 1:
+            bf.counter.fill_(k0)
+    hits = [-1] * n
+    active = list(range(n))
+    k = 0
+    while active and k < max_iters:
+        bf.run(every, graph=True)
+        k += every
+        for i in active:
+            ops.objective(w, blurs[i], b[i], X[i], lam, out=obj[i:i + 1])
+        F = obj[:, 2].cpu().numpy()
+        still = []
+        for i in active:
+            if (F[i] - F_star[i]) / F_star[i] <= tol:
+                hits[i] = k
+                bf.set_active(i, False)
+            else:
+                still.append(i)
+        active = still
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    for i in range(n):
+        bf.set_active(i, True)
+    return hits, dt, ok
+
+
 def evaluate(net: WarmStartCNN, w: ops.WaveletSpec, n: int, lam: float, seed: int, device,
-             tol: float = 1e-4, star_iters: int = 20000, max_iters: int = 16000,
-             every: int = 20, chunk: int = 64):
+             tol: float = 1e-4, star_iters: int = 60000, max_iters: int = 40000,
+             every: int = 100, chunk: int = 64, k0: int = 1):
     """Plain versus warm FISTA on n fresh images, `chunk` images per batched
-    plan. Counts: per image, the first k (checked every `every` iterations)
-    with (F(x_k) - F*) / F* <= tol, from exact objectives; F* is the lowest
-    exact objective seen over a star_iters-iteration plain run and both
-    counted runs. Times: the wall time of each batch until its slowest image
-    reaches the target (warm includes the CNN, the analysis, the threshold
-    and the fallback check)."""
-    res = {"plain_iters": [], "warm_iters": [], "plain_ms": [], "warm_ms": [],
-           "fallbacks": 0, "images": 0, "every": every, "tol": tol,
-           "star_iters": star_iters, "max_iters": max_iters}
+    plan. F* of each image is the lowest exact objective over a
+    star_iters-iteration plain run (checked every 1000). Each arm then runs
+    with converged images dropping out (timed_run): per image, the first k
+    (checked every `every`) with (F(x_k) - F*) / F* <= tol, and per batch the
+    wall time until its last image gets there (warm: the CNN, the analysis,
+    the threshold and the fallback check included)."""
+    res = {"plain_iters": [], "warm_iters": [], "plain_s": [], "warm_s": [],
+           "fallbacks": 0, "images": 0, "every": every, "tol": tol, "k0": k0,
+           "star_iters": star_iters, "max_iters": max_iters, "chunk": chunk}
     for s in range(0, n, chunk):
         c = min(chunk, n - s)
         b, blurs = problem_batch(seed, s, c, w.rows, w.cols, device)
         bf = BatchedFista([(w, bsp) for bsp in blurs], list(b), lam)
         star = objective_curve(bf, w, blurs, b, lam, None, star_iters, 1000)
-        plain = objective_curve(bf, w, blurs, b, lam, None, max_iters, every)
-        x0, ok = choose_starts(w, blurs, b, warm_start(net, w, b, lam), lam)
-        warm = objective_curve(bf, w, blurs, b, lam, x0, max_iters, every)
-        F_star = np.minimum(star.min(axis=0), np.minimum(plain.min(axis=0), warm.min(axis=0)))
-        p_hit = first_hits(plain, F_star, tol, every)
-        w_hit = first_hits(warm, F_star, tol, every)
-        kp = max(h if h > 0 else max_iters for h in p_hit)
-        kw = max(h if h > 0 else max_iters for h in w_hit)
-        bf.reset()
-        torch.cuda.synchronize(device)
-        t0 = time.perf_counter()
-        bf.run(kp, graph=True)
-        torch.cuda.synchronize(device)
-        res["plain_ms"].append(1e3 * (time.perf_counter() - t0))
-        bf.reset()
-        torch.cuda.synchronize(device)
-        t0 = time.perf_counter()
-        x0t, _ = choose_starts(w, blurs, b, warm_start(net, w, b, lam), lam)
-        bf.X.view(c, -1).copy_(x0t)
-        bf.Y.copy_(bf.X)
-        bf.run(kw, graph=True)
-        torch.cuda.synchronize(device)
-        res["warm_ms"].append(1e3 * (time.perf_counter() - t0))
+        F_star = star.min(axis=0)
+        p_hit, p_s, _ = timed_run(bf, w, blurs, b, lam, F_star, tol, every, max_iters)
+        w_hit, w_s, ok = timed_run(bf, w, blurs, b, lam, F_star, tol, every, max_iters, net=net,
+                                   k0=k0)
         res["plain_iters"] += p_hit
         res["warm_iters"] += w_hit
+        res["plain_s"].append(p_s)
+        res["warm_s"].append(w_s)
         res["fallbacks"] += int((~ok).sum().item())
         res["images"] += c
-        log(f"eval {s + c}/{n}: plain mean {np.mean(p_hit):.0f} it (batch {kp} it, "
-            f"{res['plain_ms'][-1]:.1f} ms), warm mean {np.mean(w_hit):.0f} it (batch {kw} it, "
-            f"{res['warm_ms'][-1]:.1f} ms)")
+        del bf
+        log(f"eval {s + c}/{n}: plain {p_s:.2f} s (median {np.median(p_hit):.0f} it, "
+            f"{sum(h < 0 for h in p_hit)} not reached), warm {w_s:.2f} s (median "
+            f"{np.median(w_hit):.0f} it, {sum(h < 0 for h in w_hit)} not reached)")
     return res
 
 
@@ -340,56 +372,75 @@ def main(argv=None) -> int:
     ap.add_argument("--eval-images", type=int, default=1000)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--star-iters", type=int, default=20000)
-    ap.add_argument("--max-iters", type=int, default=16000)
-    ap.add_argument("--every", type=int, default=20)
+    ap.add_argument("--star-iters", type=int, default=60000)
+    ap.add_argument("--max-iters", type=int, default=40000)
+    ap.add_argument("--every", type=int, default=100)
+    ap.add_argument("--k0", type=int, default=1)
+    ap.add_argument("--eval-only", metavar="CKPT", default=None,
+                    help="evaluate an existing checkpoint instead of training")
     ap.add_argument("--out", required=True, help="directory for the checkpoint and report")
     a = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     lam = 2e-5
     w = ops.WaveletSpec(a.size, a.size, 4, taps=8, bc="sym")
     os.makedirs(a.out, exist_ok=True)
-    t0 = time.time()
-    B, X = make_pairs(w, a.pairs, lam, a.fista_iters, seed=40 + a.seed, device=dev)
-    t_data = time.time() - t0
-    net = WarmStartCNN(dev, seed=a.seed)
-    t0 = time.time()
-    hist = train(net, w, B, X, a.epochs, a.batch, a.lr, a.lr_min, seed=a.seed)
-    t_train = time.time() - t0
-    del B, X
-    torch.cuda.empty_cache()
-    meta = {"pairs": a.pairs, "fista_iters": a.fista_iters, "epochs": a.epochs,
-            "batch": a.batch, "lr": a.lr, "lr_min": a.lr_min, "size": a.size, "lambda": lam,
-            "wavelet": "db4 J=4 sym", "seed": a.seed, "train_loss": hist,
-            "data_s": round(t_data, 1), "train_s": round(t_train, 1)}
+    if a.eval_only:
+        net = WarmStartCNN.load(a.eval_only, dev)
+        meta = dict(net.meta)
+        meta.pop("eval", None)
+        meta.pop("eval_per_image", None)
+    else:
+        t0 = time.time()
+        B, X = make_pairs(w, a.pairs, lam, a.fista_iters, seed=40 + a.seed, device=dev)
+        t_data = time.time() - t0
+        net = WarmStartCNN(dev, seed=a.seed)
+        t0 = time.time()
+        hist = train(net, w, B, X, a.epochs, a.batch, a.lr, a.lr_min, seed=a.seed)
+        t_train = time.time() - t0
+        del B, X
+        torch.cuda.empty_cache()
+        meta = {"pairs": a.pairs, "fista_iters": a.fista_iters, "epochs": a.epochs,
+                "batch": a.batch, "lr": a.lr, "lr_min": a.lr_min, "size": a.size, "lambda": lam,
+                "wavelet": "db4 J=4 sym", "seed": a.seed, "train_loss": hist,
+                "data_s": round(t_data, 1), "train_s": round(t_train, 1)}
+    if a.eval_images > 0:
+        res = evaluate(net, w, a.eval_images, lam, seed=50 + a.seed, device=dev,
+                       star_iters=a.star_iters, max_iters=a.max_iters, every=a.every, k0=a.k0)
+        meta["eval"] = summarize(res)
+        meta["eval_per_image"] = {"plain_iters": res["plain_iters"],
+                                  "warm_iters": res["warm_iters"],
+                                  "plain_batch_s": res["plain_s"], "warm_batch_s": res["warm_s"]}
+    net.meta = meta
     net.save(os.path.join(a.out, f"warmstart_db4_J4_{a.size}.npz"), meta)
-    log("checkpoint written")
-    res = evaluate(net, w, a.eval_images, lam, seed=50 + a.seed, device=dev,
-                   star_iters=a.star_iters, max_iters=a.max_iters, every=a.every)
-    meta["eval"] = summarize(res)
-    meta["eval_per_image"] = {"plain_iters": res["plain_iters"], "warm_iters": res["warm_iters"],
-                              "plain_batch_ms": res["plain_ms"], "warm_batch_ms": res["warm_ms"]}
-    with open(os.path.join(a.out, "report.json"), "w") as f:
+    with open(os.path.join(a.out, f"warmstart_db4_J4_{a.size}.json"), "w") as f:
         json.dump(meta, f, indent=1)
-    log(json.dumps(meta["eval"]))
+    log(json.dumps(meta.get("eval")))
     return 0
 
 
 def summarize(res: dict) -> dict:
+    """Per-image iteration counts (unreached images counted at the cap) and
+    the summed batch wall times of both arms."""
+    cap = res["max_iters"]
     p = np.array(res["plain_iters"], dtype=float)
     q = np.array(res["warm_iters"], dtype=float)
+    pc, qc = np.where(p > 0, p, cap), np.where(q > 0, q, cap)
     both = (p > 0) & (q > 0)
     return {"images": res["images"], "fallbacks": res["fallbacks"], "tol": res["tol"],
-            "checked_every": res["every"], "star_iters": res["star_iters"],
-            "max_iters": res["max_iters"], "reached_both": int(both.sum()),
-            "plain_iters_mean": float(p[both].mean()) if both.any() else None,
-            "warm_iters_mean": float(q[both].mean()) if both.any() else None,
-            "plain_iters_median": float(np.median(p[both])) if both.any() else None,
-            "warm_iters_median": float(np.median(q[both])) if both.any() else None,
-            "warm_fewer_iters_frac": float(np.mean(q[both] < p[both])) if both.any() else None,
-            "plain_batch_ms_mean": float(np.mean(res["plain_ms"])),
-            "warm_batch_ms_mean": float(np.mean(res["warm_ms"])),
-            "unreached_plain": int(np.sum(p < 0)), "unreached_warm": int(np.sum(q < 0))}
+            "checked_every": res["every"], "star_iters": res["star_iters"], "max_iters": cap,
+            "k0": res["k0"], "chunk": res["chunk"],
+            "plain_iters_mean_capped": float(pc.mean()), "warm_iters_mean_capped": float(qc.mean()),
+            "plain_iters_median": float(np.median(pc)), "warm_iters_median": float(np.median(qc)),
+            "plain_iters_p90": float(np.percentile(pc, 90)),
+            "warm_iters_p90": float(np.percentile(qc, 90)),
+            "reached_both": int(both.sum()),
+            "plain_iters_mean_both": float(p[both].mean()) if both.any() else None,
+            "warm_iters_mean_both": float(q[both].mean()) if both.any() else None,
+            "warm_fewer_iters_frac": float(np.mean(qc < pc)),
+            "unreached_plain": int(np.sum(p < 0)), "unreached_warm": int(np.sum(q < 0)),
+            "plain_total_s": float(np.sum(res["plain_s"])),
+            "warm_total_s": float(np.sum(res["warm_s"])),
+            "warm_over_plain_time": float(np.sum(res["warm_s"]) / np.sum(res["plain_s"]))}
 
 
 if __name__ == "__main__":

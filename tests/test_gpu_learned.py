@@ -106,10 +106,14 @@ def test_fallback_rule_rejects_bad_starts():
 def test_trained_network_start_and_iterations():
     """What the trained network gives on fresh 512 x 512 images (a stream the
     training never saw): a start whose objective is orders of magnitude below
-    F(0) and closer to x* than the analysis of b alone, no fallback, and FISTA
-    from it reaching the 1e-4 relative objective in about as many iterations
-    as from zero (the slowly converging fine-scale components of x*, which
-    neither start carries, set the count)."""
+    F(0) and closer to a 1000-iteration FISTA solution than the analysis of b
+    alone, no fallback, and FISTA from it reaching the 1e-4 relative
+    objective in about as many iterations as from zero, batch wall time with
+    converged images dropping out included. No gain in iterations is
+    asserted because none was measured: over 1000 images the warm batches took
+    0.985x the plain time, over 128 others 1.034x (the slowly converging
+    fine-scale components of x*, which neither start carries, set the
+    count)."""
     net = learned.WarmStartCNN.load(CKPT, DEV)
     lam, n = LAM, 8
     w = ops.WaveletSpec(512, 512, 4, taps=8, bc="sym")
@@ -127,9 +131,10 @@ def test_trained_network_start_and_iterations():
     d_net = ops.sq_error(x0, x_t).item()
     d_ana = ops.sq_error(xa, x_t).item()
     assert d_net < 0.95 * d_ana, (d_net, d_ana)
-    res = learned.evaluate(net, w, n, lam, seed=70, device=DEV, star_iters=16000,
-                           max_iters=12000, every=40, chunk=n)
+    res = learned.evaluate(net, w, n, lam, seed=70, device=DEV, star_iters=20000,
+                           max_iters=16000, every=100, chunk=n)
     s = learned.summarize(res)
     print(s)
-    assert s["reached_both"] >= n - 2, s
-    assert s["warm_iters_mean"] <= 1.15 * s["plain_iters_mean"], s
+    assert s["fallbacks"] == 0 and s["reached_both"] >= n - 2, s
+    assert s["warm_iters_mean_capped"] <= 1.15 * s["plain_iters_mean_capped"], s
+    assert s["warm_total_s"] <= 1.25 * s["plain_total_s"], s
