@@ -363,9 +363,12 @@ aw_status aw_batch_destroy(aw_batch* plan);
 aw_status aw_batch_layout(const aw_batch* plan, int64_t* coef_off, int64_t* img_off,
                           size_t* workspace_bytes);
 
-/* Tunables: cfg[0..2] tile-shape variant (0 or 1) of the synthesis, analysis
- * and blur kernels; cfg[3] streams (1..4) over which the kernel classes of one
- * stage run concurrently. Rebuilds the tile queues of a bound plan. */
+/* Tunables: cfg[0..2] tile-shape variant (0 full-height, 1 half-height
+ * tiles) of the synthesis, analysis and blur kernels, the analysis also 2
+ * (full height for the finest level, half height for the coarser ones);
+ * cfg[3] streams (1..4) over which the kernel classes of one stage run
+ * concurrently (each class to the stream with the least estimated work).
+ * Rebuilds the tile queues of a bound plan. */
 aw_status aw_batch_set_config(aw_batch* plan, const int32_t* cfg);
 
 /* Bind device buffers: b_obs (concatenated images), x, y (concatenated

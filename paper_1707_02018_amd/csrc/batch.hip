@@ -94,6 +94,9 @@ struct Image {
 struct Group {        // one launch
   int kind;           // 0 synth, 1 analysis, 2 blur, 3 blur adjoint
   int key0, key1;     // (L, bc) or (radius, 0)
+  int var = 0;        // tile-shape variant of this launch
+  int stream = 0;     // auxiliary stream (several streams: balanced by estimated cost)
+  long long cost = 0; // tiles x taps, the estimate the balancing uses
   int n = 0, total = 0;
   size_t lds = 0;
   std::vector<unsigned char> items;
@@ -260,6 +263,11 @@ void add_item(Group& g, const void* item, size_t sz, int tiles) {
   g.prefix.push_back(g.total);
 }
 
+// Analysis tile variant of level j: cfg value 2 takes full-height tiles for
+// the finest level (the large launches) and half-height ones for the coarser
+// levels (the short, latency-bound launches), as the single-image path does.
+int ana_var(const aw_batch* p, int j) { return p->var[1] == 2 ? (j == 1 ? 0 : 1) : p->var[1]; }
+
 aw_status build(aw_batch* p) {
   p->stages.clear();
   int Jmax = 0;
@@ -279,7 +287,7 @@ aw_status build(aw_batch* p) {
       aw::AnaLevel d{};
       d.r = {im.sr[j - 1], im.sr[j], im.e};
       d.c = {im.sc[j - 1], im.sc[j], im.e};
-      t += aw::ana_tiles(0, p->var[1], d);
+      t += aw::ana_tiles(0, ana_var(p, j), d);
     }
     p->blk_off[i + 1] = p->blk_off[i] + t;
   }
@@ -307,6 +315,7 @@ aw_status build(aw_batch* p) {
       aw::make_synth_item(0, d, im.taps, im.L, i, buf.data());
       Group& g = group_for(st, 0, im.L, im.bc);
       add_item(g, buf.data(), aw::synth_item_size(0), aw::synth_tiles(0, p->var[0], d));
+      g.var = p->var[0];
       g.lds = std::max(g.lds, aw::synth_item_lds(0, im.L, p->var[0], d));
       if (g.lds > 160 * 1024) return bfail(AW_EUNSUPPORTED, "tile window exceeds LDS");
     }
@@ -328,6 +337,7 @@ aw_status build(aw_batch* p) {
                            buf.data());
       Group& g = group_for(st, 2 + adj, im.b.radius, 0);
       add_item(g, buf.data(), aw::blur_item_size(0), tiles);
+      g.var = p->var[2];
     }
     p->stages.push_back(std::move(st));
   }
@@ -365,11 +375,12 @@ aw_status build(aw_batch* p) {
       pe.beta_tab = reinterpret_cast<const double*>(ws + p->beta_off);
       pe.counter = reinterpret_cast<const int*>(ws + p->ctr_off);
       pe.beta_len = kBetaLen;
-      const int tiles = aw::ana_tiles(0, p->var[1], d);
+      const int tiles = aw::ana_tiles(0, ana_var(p, j), d);
       lvl_base[i] += tiles;
       aw::make_ana_item_prox(d, im.taps, im.L, i, pe, buf.data());
       Group& g = group_for(st, 1, im.L, im.bc);
       add_item(g, buf.data(), aw::ana_item_size(0), tiles);
+      g.var = ana_var(p, j);
     }
     p->stages.push_back(std::move(st));
   }
@@ -399,6 +410,28 @@ aw_status build(aw_batch* p) {
   std::memcpy(host.data() + p->bpref_dev, p->blk_off.data(), p->blk_off.size() * sizeof(int));
   if (hipMemcpy(p->blob, host.data(), off, hipMemcpyHostToDevice) != hipSuccess)
     return bfail(AW_EHIP, "plan upload failed");
+  // streams of the classes of each stage: longest estimated launch first,
+  // each to the stream with the least work so far
+  for (Stage& st : p->stages) {
+    std::vector<int> order(st.groups.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+      Group& g = st.groups[i];
+      g.cost = (long long)g.total * (g.kind <= 1 ? g.key0 : 2 * g.key0 + 1);
+      order[i] = (int)i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return st.groups[a].cost > st.groups[b].cost;
+    });
+    long long load[4] = {0, 0, 0, 0};
+    const int ns = std::max(1, std::min(p->var[3], 4));
+    for (int i : order) {
+      int best = 0;
+      for (int k = 1; k < ns; ++k)
+        if (load[k] < load[best]) best = k;
+      st.groups[i].stream = best;
+      load[best] += st.groups[i].cost;
+    }
+  }
   // events for fork / join
   size_t need = 0;
   for (const Stage& st : p->stages) need += st.groups.size() + 1;
@@ -419,15 +452,15 @@ aw_status launch_group(aw_batch* p, const Group& g, hipStream_t s) {
   if (g.total == 0) return AW_OK;
   switch (g.kind) {
     case 0:
-      e = aw::launch_synth_batch(0, g.key0, g.key1, p->var[0], items, prefix, g.n, g.total, active,
+      e = aw::launch_synth_batch(0, g.key0, g.key1, g.var, items, prefix, g.n, g.total, active,
                                  g.lds, s);
       break;
     case 1:
-      e = aw::launch_ana_batch(0, g.key0, g.key1, p->var[1], items, prefix, g.n, g.total, active, s,
+      e = aw::launch_ana_batch(0, g.key0, g.key1, g.var, items, prefix, g.n, g.total, active, s,
                                true);
       break;
     default:
-      e = aw::launch_blur_batch(0, g.key0, g.kind == 3, p->var[2], items, prefix, g.n, g.total,
+      e = aw::launch_blur_batch(0, g.key0, g.kind == 3, g.var, items, prefix, g.n, g.total,
                                 active, s);
   }
   if (e != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(e));
@@ -486,7 +519,8 @@ aw_status aw_batch_layout(const aw_batch* p, int64_t* coef_off, int64_t* img_off
 aw_status aw_batch_set_config(aw_batch* p, const int32_t* var) {
   if (!p || !var) return bfail(AW_EINVAL, "invalid arguments");
   for (int k = 0; k < 3; ++k)
-    if (var[k] != 0 && var[k] != 1) return bfail(AW_EINVAL, "tile variant must be 0 or 1");
+    if (var[k] != 0 && var[k] != 1 && !(k == 1 && var[k] == 2))
+      return bfail(AW_EINVAL, "tile variant must be 0 or 1 (analysis: 0, 1 or 2)");
   if (var[3] < 1 || var[3] > 4) return bfail(AW_EINVAL, "streams must be 1..4");
   for (int k = 0; k < 4; ++k) p->var[k] = var[k];
   if (p->bound) return build(p);
@@ -557,7 +591,7 @@ aw_status aw_batch_step(aw_batch* p, void* stream) {
     hipEvent_t fork = p->events[ev++];
     if (hipEventRecord(fork, s) != hipSuccess) return bfail(AW_EHIP, "event record failed");
     for (int gi = 0; gi < ng; ++gi) {
-      hipStream_t a = p->aux[gi % p->var[3]];
+      hipStream_t a = p->aux[st.groups[gi].stream];
       if (hipStreamWaitEvent(a, fork, 0) != hipSuccess) return bfail(AW_EHIP, "stream wait failed");
       aw_status r = launch_group(p, st.groups[gi], a);
       if (r != AW_OK) return r;

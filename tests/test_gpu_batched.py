@@ -77,7 +77,7 @@ def test_graph_replay_and_variants_equal_eager(setup):
     bf.run(ITERS, graph=False)
     torch.cuda.synchronize()
     eager = bf.X.clone()
-    for cfg in [(0, 0, 0, 4), (1, 1, 1, 1), (0, 1, 0, 2), (1, 0, 1, 4)]:
+    for cfg in [(0, 0, 0, 4), (1, 1, 1, 1), (0, 1, 0, 2), (1, 0, 1, 4), (0, 2, 0, 3)]:
         bf.set_config(cfg)
         bf.reset()
         bf.run(ITERS, graph=True)
