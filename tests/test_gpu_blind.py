@@ -66,7 +66,7 @@ def test_multichannel_conv_pair(dt, C, K, N):
     assert load().aw_conv_multichannel(code, C, K, N, ops._ptr(hd), ops._ptr(sd), ops._ptr(xd),
                                        ops._ptr(r), ops._ptr(gh), ops._ptr(parts), ops._ptr(gs),
                                        ops._ptr(rn), _stream()) == 0
-    tol = 10 * TOL[dt]
+    tol = TOL[dt]  # FP32 rounding of these sums measures about 1e-7
     assert rel(host(r), r_ref) <= tol
     assert rel(host(gh), gh_ref) <= tol
     assert rel(host(gs), gs_ref) <= tol
