@@ -191,6 +191,8 @@ def parse():
                     help="run only the uneven-batch section and print its JSON (for profiling)")
     ap.add_argument("--only-conv", action="store_true",
                     help="run only the convolution-pair section and print its JSON (for profiling)")
+    ap.add_argument("--only-dct", action="store_true",
+                    help="run only the DCT-II blur section and print its JSON (for profiling)")
     ap.add_argument("--warm-images", type=int, default=16)
     ap.add_argument("--only-step", type=int, default=0, metavar="STEPS",
                     help="run only STEPS FISTA steps at the bench size (for profiler passes)")
@@ -781,6 +783,9 @@ def main():
         return
     if args.only_conv:
         print(json.dumps(bench_conv(torch, ops)))
+        return
+    if args.only_dct:
+        print(json.dumps(bench_blur_dct(torch, ops, _lib.load(), torch.cuda.Stream(device=dev))))
         return
     if args.copy_reference:
         src = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device=dev)

@@ -174,8 +174,9 @@ aw_status blur_adjoint(const aw_blur* b, aw_dtype dtype, int32_t batch, const vo
  * kernels for wide PSFs). With half-point reflexive boundaries (repeating with
  * period 2N) and a symmetric PSF g of any radius, each axis of R is
  * C^{-1} diag(lambda) C with C the DCT-II and lambda_k = g_0 + 2 sum_{u>=1}
- * g_u cos(pi k u / N); then R^* = R. The plan holds the eigenvalues of both
- * axes (device memory, freed by destroy). rows and cols: powers of two in
+ * g_u cos(pi k u / N); then R^* = R. The plan holds the eigenvalues and the
+ * FFT / DCT twiddle tables of both axes, computed on the host in FP64 and
+ * stored in the plan's dtype (device memory, freed by destroy). rows and cols: powers of two in
  * [2, 4096]; taps: host array of 2*radius+1 doubles, symmetric to 1e-14
  * relative (else AW_EUNSUPPORTED), 0 <= radius <= 16384. */
 typedef struct aw_blur_dct aw_blur_dct;

@@ -928,7 +928,10 @@ aw_status conv_adjoint_pair(aw_dtype dtype, int32_t batch, int32_t K, int32_t N,
 struct aw_blur_dct {
   int rows = 0, cols = 0, radius = 0;
   aw_dtype dtype = AW_F32;
-  void* lam = nullptr;  // eigenvalues: rows values (rows axis), then cols values
+  // one device buffer in the plan's dtype: eigenvalues of the rows axis (rows
+  // values) and of the columns axis (cols), then the FFT and DCT twiddles of
+  // the rows axis (2 rows values each, complex pairs) and of the columns axis
+  void* lam = nullptr;
 };
 
 static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
@@ -963,6 +966,18 @@ aw_status aw_blur_dct_create(int32_t rows, int32_t cols, int32_t radius, const d
       double v = taps[radius];
       for (int u = 1; u <= radius; ++u) v += 2.0 * taps[radius + u] * std::cos(M_PI * k * u / N);
       L[k] = v;
+    }
+  }
+  // twiddles of each axis, FP64 on the host: exp(-2 pi i j / N), exp(-i pi k / 2N)
+  for (int axis = 0; axis < 2; ++axis) {
+    const int N = axis ? cols : rows;
+    for (int j = 0; j < N; ++j) {  // angles reduced to [0, 2 pi) exactly: j / N in [0, 1)
+      lam.push_back(std::cos(2.0 * M_PI * j / N));
+      lam.push_back(-std::sin(2.0 * M_PI * j / N));
+    }
+    for (int k = 0; k < N; ++k) {
+      lam.push_back(std::cos(M_PI * k / (2.0 * N)));
+      lam.push_back(-std::sin(M_PI * k / (2.0 * N)));
     }
   }
   aw_blur_dct* p = new aw_blur_dct;
@@ -1014,9 +1029,17 @@ aw_status aw_blur_dct_apply(const aw_blur_dct* plan, int32_t batch, const void* 
   if ((st = need_ws(workspace, workspace_bytes, need)) != AW_OK) return st;
   const size_t half = need / 2;
   const int di = plan->dtype == AW_F64;
-  const char* lam = static_cast<const char*>(plan->lam);
-  st = hip_check(aw::launch_blur_dct(di, plan->rows, plan->cols, batch, lam,
-                                     lam + plan->rows * dsize(plan->dtype), x, y, workspace,
+  const char* base = static_cast<const char*>(plan->lam);
+  const size_t es = dsize(plan->dtype);
+  const size_t R = plan->rows, C = plan->cols;
+  aw::DctTables tb;
+  tb.lam_r = base;
+  tb.lam_c = base + R * es;
+  tb.fft_r = base + (R + C) * es;
+  tb.dct_r = base + (3 * R + C) * es;
+  tb.fft_c = base + (5 * R + C) * es;
+  tb.dct_c = base + (5 * R + 3 * C) * es;
+  st = hip_check(aw::launch_blur_dct(di, plan->rows, plan->cols, batch, tb, x, y, workspace,
                                      wsp(workspace, half), (hipStream_t)stream),
                  "DCT blur launch");
   return st == AW_OK ? ok() : st;

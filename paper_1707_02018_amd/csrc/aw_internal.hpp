@@ -371,13 +371,18 @@ hipError_t launch_conv_pair(int dtype, int batch, int K, int N, const void* h, c
                             const void* x_obs, void* resid, void* grad_h, void* grad_s,
                             hipStream_t st, bool shared_s = false);
 
-// R by DCT-II diagonalisation (dct.hip): lam_r / lam_c are the eigenvalues
-// along the rows axis (length rows) and the columns axis (length cols); w1, w2
-// hold batch * rows * cols values each; x may alias y.
+// R by DCT-II diagonalisation (dct.hip). Device tables in the transform's
+// dtype: lam_r / lam_c the eigenvalues along the rows axis (length rows) and
+// the columns axis (length cols); fft_* [N] complex exp(-2 pi i j / N) and
+// dct_* [N] complex exp(-i pi k / 2N) for N = rows (_r) and N = cols (_c),
+// complex values as (re, im) pairs. w1, w2 hold batch * rows * cols values
+// each; x may alias y.
+struct DctTables {
+  const void *lam_r, *lam_c, *fft_r, *dct_r, *fft_c, *dct_c;
+};
 size_t blur_dct_lds(int dtype, int n);
-hipError_t launch_blur_dct(int dtype, int rows, int cols, int batch, const void* lam_r,
-                           const void* lam_c, const void* x, void* y, void* w1, void* w2,
-                           hipStream_t s);
+hipError_t launch_blur_dct(int dtype, int rows, int cols, int batch, const DctTables& tb,
+                           const void* x, void* y, void* w1, void* w2, hipStream_t s);
 
 // Multi-channel blind channel estimation helpers (blind.hip).
 hipError_t launch_sum_rows(int dtype, int rows, long long n, const void* in, void* out,

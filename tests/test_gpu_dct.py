@@ -26,8 +26,11 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# sizes cover the any-length row kernel (2 .. 256), the compile-time pass
+# structures (512 .. 4096: radix 8 passes ending in 8, 2, 4 and 8) and both
+# transposes (32 x 32 scalar tiles, 64 x 64 vector tiles)
 CASES = [(16, 16, 0), (16, 16, 5), (64, 32, 7), (32, 64, 40), (256, 512, 12), (256, 256, 200),
-         (8, 128, 300), (2, 4, 3), (1024, 256, 60)]
+         (8, 128, 300), (2, 4, 3), (1024, 256, 60), (16, 4096, 9), (4096, 8, 3), (128, 2048, 5)]
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
