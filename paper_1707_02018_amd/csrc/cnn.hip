@@ -5,10 +5,13 @@
 // channels, N = 32 pixels of one image row, K = 16 input channels per tap half.
 // Each wave owns a 32-pixel column strip and slides down its rows: one input
 // row's three shifted fragments feed the three output rows that need them, so
-// every fragment is loaded once and used by three taps. The weights of all
-// nine taps stay in registers for the whole strip. The same kernel runs the
-// input gradient (mirrored, transposed weights) with the ReLU mask of the
-// layer below applied in its epilogue.
+// every fragment is read once and used by three taps. The four waves of a
+// workgroup own adjacent strips and stage each input row once in a ring of
+// LDS rows (coalesced 16-byte loads issued two rows ahead), from which each
+// wave reads its shifted fragments. The weights of all nine taps stay in
+// registers for the whole strip. The same kernel runs the input gradient
+// (mirrored, transposed weights) with the ReLU mask of the layer below applied
+// in its epilogue.
 //
 // The weight gradient is a K = pixels contraction, so both operands are
 // staged through LDS transposed to channel-major rows; the three horizontal
@@ -110,58 +113,82 @@ constexpr int kPackJobs = 288 + 32 + 4 * (2 * 9216 + 32) + 9216 + 32 + 288;
 // ------------------------------------------------------- 1 -> 32 (VALU)
 // FWD:  y[p][c] = relu(bias[c] + sum_t w[t][c] src[p + off(t)])   (src = the FP32 image)
 // else: y[p][c] = [mask[p][c] > 0] sum_t w[t][c] rnd(src[p + off(t)])   (src = a gradient)
-// One thread per (pixel, group of 8 channels); off(t) = (t / 3 - 1, t % 3 - 1).
+// One thread per (pixel column, group of 8 channels) and kInRows rows;
+// off(t) = (t / 3 - 1, t % 3 - 1). No thread divides a pixel index.
 // The image keeps FP32: its noise (1e-3) is below the BF16 step near 1 (2^-8).
+constexpr int kInRows = 16;  // output rows per thread
+
 template <bool FWD>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ src,
                                                       const uint16_t* __restrict__ w,
                                                       const float* __restrict__ bias,
                                                       const uint16_t* __restrict__ mask,
-                                                      uint16_t* __restrict__ y, int H, int W,
-                                                      long long npix) {
-  const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = gid >> 2;
-  const int g = (int)(gid & 3);
-  if (p >= npix) return;
-  const int x = (int)(p % W);
-  const long long q = p / W;
-  const int r = (int)(q % H);
-  const float* s = src + (q / H) * (long long)H * W;
-  float in[9];
+                                                      uint16_t* __restrict__ y, int H, int W) {
+  // grid: (4 W / 256 rounded up, H / kInRows rounded up, images); a thread
+  // walks kInRows rows of one (pixel column, channel group) with the weights
+  // in registers and a sliding 3 x 3 window of inputs
+  const int gx = blockIdx.x * 256 + threadIdx.x;
+  const int x = gx >> 2, g = gx & 3;
+  if (x >= W) return;
+  const int r0 = blockIdx.y * kInRows;
+  const int r1 = min(r0 + kInRows, H);
+  const long long plane = (long long)H * W;
+  const float* s = src + (long long)blockIdx.z * plane;
+  const long long pbase = (long long)blockIdx.z * plane + x;
+  u32x4 wv[9];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
-    const float v = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
-    in[t] = FWD ? v : rnd_bf(v);
-  }
-  float acc[8];
+  for (int t = 0; t < 9; ++t) wv[t] = ld16(w + t * 32 + 8 * g);
+  float b8[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = FWD ? bias[8 * g + j] : 0.0f;
+  for (int j = 0; j < 8; ++j) b8[j] = FWD ? bias[8 * g + j] : 0.0f;
+  auto in_row = [&](int rr, float (&v)[3]) {
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const u32x4 wv = ld16(w + t * 32 + 8 * g);
+    for (int k = 0; k < 3; ++k) {
+      const int cc = x + k - 1;
+      const float u = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
+      v[k] = FWD ? u : rnd_bf(u);
+    }
+  };
+  float in[3][3];  // rows r - 1, r, r + 1
+  in_row(r0 - 1, in[0]);
+  in_row(r0, in[1]);
+  for (int r = r0; r < r1; ++r) {
+    in_row(r + 1, in[2]);
+    const long long p = pbase + (long long)r * W;
+    u32x4 mk = {0, 0, 0, 0};
+    if (!FWD) mk = ld16(mask + p * 32 + 8 * g);
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = b8[j];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const float iv = in[t / 3][t % 3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[2 * j] += bf2f(wv[t][j] & 0xffffu) * iv;
+        acc[2 * j + 1] += bf2f(wv[t][j] >> 16) * iv;
+      }
+    }
+    u32x4 out;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      acc[2 * j] += bf2f(wv[j] & 0xffffu) * in[t];
-      acc[2 * j + 1] += bf2f(wv[j] >> 16) * in[t];
+      float a0 = acc[2 * j], a1 = acc[2 * j + 1];
+      if (FWD) {
+        a0 = fmaxf(a0, 0.0f);
+        a1 = fmaxf(a1, 0.0f);
+      } else {
+        if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
+        if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
+      }
+      out[j] = f2bf(a0) | (f2bf(a1) << 16);
     }
-  }
-  u32x4 mk = {0, 0, 0, 0};
-  if (!FWD) mk = ld16(mask + p * 32 + 8 * g);
-  u32x4 out;
+    *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float a0 = acc[2 * j], a1 = acc[2 * j + 1];
-    if (FWD) {
-      a0 = fmaxf(a0, 0.0f);
-      a1 = fmaxf(a1, 0.0f);
-    } else {
-      if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
-      if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+      in[0][k] = in[1][k];
+      in[1][k] = in[2][k];
     }
-    out[j] = f2bf(a0) | (f2bf(a1) << 16);
   }
-  *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
 }
 
 // ------------------------------------------------------- 32 -> 32 (MFMA)
@@ -175,7 +202,7 @@ struct ConvArgs {
   uint16_t* y;           // [n][H][W][32] (kFwd, kDgrad)
   const float* base;     // [n][H][W] (kOut): added to output channel 0
   float* out;            // [n][H][W] (kOut)
-  int H, W, strips, bands, total_waves;
+  int n, H, W, strips, bands, groups;  // groups: workgroups per band (kConvStrips strips each)
 };
 
 constexpr int kConvR = 16;  // output rows per wave; (kConvR + 2) % 3 == 0
@@ -192,49 +219,113 @@ __device__ __forceinline__ f32x16& pick(f32x16& a, f32x16& b, f32x16& c) {
   else return c;
 }
 
-__device__ __forceinline__ void load_row(Frags& F, const uint16_t* X, int H, int W, int r, int x,
-                                         int h) {
+// A workgroup (four waves) owns kConvStrips adjacent 32-pixel strips of one
+// 16-row band. Its input rows are staged in a ring of three LDS rows: pixels
+// x0 - 1 .. x0 + 128 (x0 = the first strip's first pixel), 32 channels each,
+// at a pitch of 40 elements (80 bytes, so the 16-byte fragment reads of a
+// wave spread over the banks). Staging is one 16-byte chunk per thread and
+// load, coalesced; the three shifted fragments of a tap row then come from LDS.
+constexpr int kConvStrips = 4;
+constexpr int kConvPx = 32 * kConvStrips + 2;
+constexpr int kConvPitch = 40;
+constexpr int kConvRowElems = kConvPx * kConvPitch;
+constexpr int kConvChunks = kConvPx * 4;
+constexpr int kConvLoads = (kConvChunks + 255) / 256;
+
+// Input row r, pixels xs .. xs + kConvPx - 1, into registers (zeros outside
+// the image).
+__device__ __forceinline__ void stage_load(u32x4 (&v)[kConvLoads], const uint16_t* X, int H, int W,
+                                           int r, int xs) {
   const bool rv = r >= 0 && r < H;
 #pragma unroll
-  for (int kx = 0; kx < 3; ++kx) {
-    const int c = x + kx - 1;
-    const bool v = rv && c >= 0 && c < W;
-    const uint16_t* p = X + ((long long)r * W + c) * 32 + 8 * h;
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) F.f[kx][kb] = v ? ld16(p + 16 * kb) : u32x4{0, 0, 0, 0};
+  for (int i = 0; i < kConvLoads; ++i) {
+    const int c = threadIdx.x + 256 * i;
+    const int col = xs + c / 4;
+    const bool ok = c < kConvChunks && rv && col >= 0 && col < W;
+    v[i] = ok ? ld16(X + ((long long)r * W + col) * 32 + 8 * (c % 4)) : u32x4{0, 0, 0, 0};
   }
 }
 
+__device__ __forceinline__ void stage_store(uint16_t* B, const u32x4 (&v)[kConvLoads]) {
+#pragma unroll
+  for (int i = 0; i < kConvLoads; ++i) {
+    const int c = threadIdx.x + 256 * i;
+    if (c < kConvChunks) *reinterpret_cast<u32x4*>(B + (c / 4) * kConvPitch + 8 * (c % 4)) = v[i];
+  }
+}
+
+// The lane's fragments of a staged row: pixel pw + kx of the row buffer
+// (pw = the wave's strip offset + lane % 32), channels 8 h + 16 kb .. + 7.
+__device__ __forceinline__ void lds_frags(Frags& F, const uint16_t* B, int pw, int h) {
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+      F.f[kx][kb] = *reinterpret_cast<const u32x4*>(B + (pw + kx) * kConvPitch + 8 * (h + 2 * kb));
+}
+
+// Output row o of the wave's strip. The 32 -> 1 layer stores channel 0
+// (lanes of h = 0, one float per pixel, contiguous). The 32 -> 32 modes round
+// to BF16 in registers (the bias read from LDS: its channels differ between
+// the two half-waves, so a global read would be a vector load per value), then
+// pass the 32 pixels x 32 channels through the
+// wave's LDS tile ob (pitch kConvPitch) so that each lane stores 16
+// contiguous bytes and each store instruction writes 1 KB of the row: lane l
+// takes pixel 16 k + l / 4, channels 8 (l % 4) .. + 7 (k = 0, 1). The ReLU
+// mask of the input gradient is applied to the rounded values (a zero rounds
+// to zero), read with the same coalesced pattern.
 template <int MODE>
 __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, long long img_off,
-                                              int o, int x, int h) {
-  if (x < a.W) {
-    const long long pix = img_off + (long long)o * a.W + x;
-    if constexpr (MODE == kOut) {
-      if (h == 0) a.out[pix] = acc[0] + a.bias[0] + a.base[pix];
-    } else {
+                                              int o, int x, int h, uint16_t* ob, int xw,
+                                              const float* sbias) {
+  if constexpr (MODE == kOut) {
+    if (x < a.W && h == 0) {
+      const long long pix = img_off + (long long)o * a.W + x;
+      a.out[pix] = acc[0] + a.bias[0] + a.base[pix];
+    }
+  } else {
+    const int xl = threadIdx.x & 31;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int co = 8 * g + 4 * h;
-        float v[4];
+    for (int g = 0; g < 4; ++g) {
+      const int co = 8 * g + 4 * h;
+      float v[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = acc[4 * g + i];
-        if constexpr (MODE == kFwd) {
+      for (int i = 0; i < 4; ++i) v[i] = acc[4 * g + i];
+      if constexpr (MODE == kFwd) {
+        const float4 bv = *reinterpret_cast<const float4*>(sbias + co);
+        v[0] = fmaxf(v[0] + bv.x, 0.0f);
+        v[1] = fmaxf(v[1] + bv.y, 0.0f);
+        v[2] = fmaxf(v[2] + bv.z, 0.0f);
+        v[3] = fmaxf(v[3] + bv.w, 0.0f);
+      }
+      u32x2 st;
+      st[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
+      st[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
+      *reinterpret_cast<u32x2*>(ob + xl * kConvPitch + co) = st;
+    }
+    // the tile is private to the wave and LDS operations of a wave complete
+    // in order; the barrier only keeps the compiler from reordering
+    __builtin_amdgcn_wave_barrier();
+    const int lane = threadIdx.x & 63;
+    const long long row = img_off + (long long)o * a.W;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i] + a.bias[co + i], 0.0f);
-        } else {
-          const u32x2 mk = *reinterpret_cast<const u32x2*>(a.mask + pix * 32 + co);
-          if (!bf_positive(mk[0] & 0xffffu)) v[0] = 0.0f;
-          if (!bf_positive(mk[0] >> 16)) v[1] = 0.0f;
-          if (!bf_positive(mk[1] & 0xffffu)) v[2] = 0.0f;
-          if (!bf_positive(mk[1] >> 16)) v[3] = 0.0f;
+    for (int k = 0; k < 2; ++k) {
+      const int p = 16 * k + (lane >> 2), c = lane & 3;
+      u32x4 v = *reinterpret_cast<const u32x4*>(ob + p * kConvPitch + 8 * c);
+      if (xw + p < a.W) {
+        const long long pix = row + xw + p;
+        if constexpr (MODE == kDgrad) {
+          const u32x4 mk = ld16(a.mask + pix * 32 + 8 * c);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (!bf_positive(mk[j] & 0xffffu)) v[j] &= 0xffff0000u;
+            if (!bf_positive(mk[j] >> 16)) v[j] &= 0x0000ffffu;
+          }
         }
-        u32x2 st;
-        st[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
-        st[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
-        *reinterpret_cast<u32x2*>(a.y + pix * 32 + co) = st;
+        *reinterpret_cast<u32x4*>(a.y + pix * 32 + 8 * c) = v;
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
@@ -251,15 +342,22 @@ __device__ __forceinline__ void conv_taps(const bf16x8 (&wa)[9][2], const Frags&
                                                     0, 0, 0);
 }
 
-// One input row r (S = (r - y0 + 1) mod 3): contributions to output rows
-// r + 1 (ky = 0), r (ky = 1), r - 1 (ky = 2); row r - 1 is then complete.
+// One input row r (S = (r - y0 + 1) mod 3, also its ring buffer): contributions
+// to output rows r + 1 (ky = 0), r (ky = 1), r - 1 (ky = 2); row r - 1 is then
+// complete. The registers pre hold row r + 2, loaded one row earlier: they go
+// to ring buffer (S + 2) mod 3 (row r - 1's, read by every wave before the
+// last barrier), and the loads of row r + 3 are issued, in flight over two
+// rows of MFMAs. Ends with the barrier that publishes row r + 2.
 template <int MODE, int S>
 __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, long long img_off,
-                                         const bf16x8 (&wa)[9][2], Frags& nxt, f32x16& a0,
-                                         f32x16& a1, f32x16& a2, int r, int y0, int yend, int x,
-                                         int h) {
-  Frags cur = nxt;
-  if (r + 1 <= yend) load_row(nxt, X, a.H, a.W, r + 1, x, h);
+                                         const bf16x8 (&wa)[9][2], uint16_t* ring,
+                                         u32x4 (&pre)[kConvLoads], f32x16& a0, f32x16& a1,
+                                         f32x16& a2, int r, int y0, int yend, int x, int h, int pw,
+                                         int xs, uint16_t* ob, const float* sbias) {
+  Frags cur;
+  lds_frags(cur, ring + S * kConvRowElems, pw, h);
+  if (r + 2 <= yend) stage_store(ring + ((S + 2) % 3) * kConvRowElems, pre);
+  if (r + 3 <= yend) stage_load(pre, X, a.H, a.W, r + 3, xs);
   if (r >= 0 && r < a.H) {
     if (r + 1 < yend) conv_taps<0>(wa, cur, pick<S>(a0, a1, a2));
     if (r >= y0 && r < yend) conv_taps<1>(wa, cur, pick<(S + 2) % 3>(a0, a1, a2));
@@ -267,24 +365,31 @@ __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, l
   }
   const int o = r - 1;
   f32x16& done = pick<(S + 1) % 3>(a0, a1, a2);
-  if (o >= y0 && o < yend) conv_epilogue<MODE>(a, done, img_off, o, x, h);
+  if (o >= y0 && o < yend)
+    conv_epilogue<MODE>(a, done, img_off, o, x, h, ob, x - (threadIdx.x & 31), sbias);
   else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) done[i] = 0.0f;
   }
+  __syncthreads();
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void conv32_kernel(ConvArgs a) {
+  __shared__ __align__(16) uint16_t ring[3 * kConvRowElems];
+  __shared__ __align__(16) uint16_t obuf[4][32 * kConvPitch];  // per wave: one output row
+  __shared__ __align__(16) float sbias[32];
+  if (MODE == kFwd && threadIdx.x < 32) sbias[threadIdx.x] = a.bias[threadIdx.x];
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wave >= a.total_waves) return;  // whole waves only
-  const int sx = wave % a.strips;
-  const int rest = wave / a.strips;
+  const int w = threadIdx.x >> 6;
+  const int sg = blockIdx.x % a.groups;
+  const int rest = blockIdx.x / a.groups;
   const int band = rest % a.bands;
   const int img = rest / a.bands;
   const int h = lane >> 5;
-  const int x = sx * 32 + (lane & 31);
+  const int pw = w * 32 + (lane & 31);
+  const int x = sg * 32 * kConvStrips + pw;  // beyond W for strips past the image: no stores
+  const int xs = sg * 32 * kConvStrips - 1;  // first staged pixel
   const int y0 = band * kConvR;
   const int yend = min(y0 + kConvR, a.H);
   const long long img_off = (long long)img * a.H * a.W;
@@ -301,12 +406,21 @@ __global__ __launch_bounds__(256) void conv32_kernel(ConvArgs a) {
   f32x16 a0, a1, a2;
 #pragma unroll
   for (int i = 0; i < 16; ++i) a0[i] = a1[i] = a2[i] = 0.0f;
-  Frags nxt;
-  load_row(nxt, X, a.H, a.W, y0 - 1, x, h);
+  // rows y0 - 1 and y0 staged, row y0 + 1 in flight
+  u32x4 pre[kConvLoads];
+  stage_load(pre, X, a.H, a.W, y0 - 1, xs);
+  stage_store(ring, pre);
+  stage_load(pre, X, a.H, a.W, y0, xs);
+  stage_store(ring + kConvRowElems, pre);
+  if (y0 + 1 <= yend) stage_load(pre, X, a.H, a.W, y0 + 1, xs);
+  __syncthreads();
   for (int r = y0 - 1; r <= yend; r += 3) {
-    conv_row<MODE, 0>(a, X, img_off, wa, nxt, a0, a1, a2, r, y0, yend, x, h);
-    conv_row<MODE, 1>(a, X, img_off, wa, nxt, a0, a1, a2, r + 1, y0, yend, x, h);
-    conv_row<MODE, 2>(a, X, img_off, wa, nxt, a0, a1, a2, r + 2, y0, yend, x, h);
+    conv_row<MODE, 0>(a, X, img_off, wa, ring, pre, a0, a1, a2, r, y0, yend, x, h, pw, xs,
+                        obuf[w], sbias);
+    conv_row<MODE, 1>(a, X, img_off, wa, ring, pre, a0, a1, a2, r + 1, y0, yend, x, h, pw, xs,
+                        obuf[w], sbias);
+    conv_row<MODE, 2>(a, X, img_off, wa, ring, pre, a0, a1, a2, r + 2, y0, yend, x, h, pw, xs,
+                        obuf[w], sbias);
   }
 }
 
@@ -489,11 +603,15 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
   for (int j = 0; j < 8; ++j) s32[j] = 0.0f;
   const long long p0 = (long long)blockIdx.x * kWinPix;
   const long long p1 = min(p0 + kWinPix, npix);
-  for (long long p = p0 + (tid >> 2); p < p1; p += 64) {
-    const int x = (int)(p % W);
-    const long long q = p / W;
-    const int r = (int)(q % H);
-    const float* s = x1 + (q / H) * (long long)H * W;
+  // the thread's pixel as (image, row, column), divided once and then
+  // advanced by 64 pixels per iteration
+  long long p = p0 + (tid >> 2);
+  int x = (int)(p % W);
+  long long q = p / W;
+  int r = (int)(q % H);
+  long long im = q / H;
+  for (; p < p1; p += 64) {
+    const float* s = x1 + im * (long long)H * W;
     float in[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -515,6 +633,14 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
       for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t];
     }
     if (g == 0) s1 += s[(long long)r * W + x];
+    x += 64;
+    while (x >= W) {
+      x -= W;
+      if (++r == H) {
+        r = 0;
+        ++im;
+      }
+    }
   }
   // lanes with the same g: reduce over lane bits 2..5 (fixed pattern)
 #pragma unroll
@@ -629,27 +755,27 @@ ConvArgs conv_args(int n, int H, int W) {
   a.W = W;
   a.strips = (W + 31) / 32;
   a.bands = (H + kConvR - 1) / kConvR;
-  a.total_waves = n * a.strips * a.bands;
+  a.groups = (a.strips + kConvStrips - 1) / kConvStrips;
+  a.n = n;
   return a;
 }
 
 template <int MODE>
 hipError_t launch_conv32(const ConvArgs& a, hipStream_t s) {
-  const int blocks = (a.total_waves + 3) / 4;
-  hipLaunchKernelGGL(conv32_kernel<MODE>, dim3(blocks), dim3(256), 0, s, a);
+  const long long blocks = (long long)a.n * a.bands * a.groups;
+  hipLaunchKernelGGL(conv32_kernel<MODE>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_conv_in(bool fwd, const float* src, const uint16_t* w, const float* bias,
                           const uint16_t* mask, uint16_t* y, int n, int H, int W, hipStream_t s) {
-  const long long npix = (long long)n * H * W;
-  const long long blocks = (npix * 4 + 255) / 256;
+  if (n > 65535) return hipErrorInvalidValue;  // grid z
+  const dim3 grid((unsigned)((4LL * W + 255) / 256), (unsigned)((H + kInRows - 1) / kInRows),
+                  (unsigned)n);
   if (fwd)
-    hipLaunchKernelGGL(conv_in_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, src, w, bias,
-                       mask, y, H, W, npix);
+    hipLaunchKernelGGL(conv_in_kernel<true>, grid, dim3(256), 0, s, src, w, bias, mask, y, H, W);
   else
-    hipLaunchKernelGGL(conv_in_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, src, w,
-                       bias, mask, y, H, W, npix);
+    hipLaunchKernelGGL(conv_in_kernel<false>, grid, dim3(256), 0, s, src, w, bias, mask, y, H, W);
   return hipGetLastError();
 }
 
