@@ -191,6 +191,8 @@ def parse():
                     help="run only the uneven-batch section and print its JSON (for profiling)")
     ap.add_argument("--only-conv", action="store_true",
                     help="run only the convolution-pair section and print its JSON (for profiling)")
+    ap.add_argument("--only-cnn", action="store_true",
+                    help="run only the warm-start CNN timing and print its JSON (for profiling)")
     ap.add_argument("--only-dct", action="store_true",
                     help="run only the DCT-II blur section and print its JSON (for profiling)")
     ap.add_argument("--warm-images", type=int, default=16)
@@ -550,6 +552,35 @@ def bench_modes(torch, ops, lib, bsp, b, lam: float, modes, steps: int = 100) ->
     return out
 
 
+def bench_cnn(torch, reps: int = 5) -> dict:
+    """Warm-start CNN at batch 64 of 512^2 (random weights): forward and
+    backward pass, ms per call from HIP events on the current stream."""
+    from paper_1707_02018_amd import learned
+
+    dev = torch.device("cuda:0")
+    net = learned.WarmStartCNN(dev, seed=0)
+    b = torch.rand(64, 512, 512, device=dev)
+    du = torch.ones_like(b)
+    for _ in range(2):
+        net.forward(b)
+        net.backward(b, du)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        net.forward(b)
+    ev[1].record()
+    for _ in range(reps):
+        net.backward(b, du)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / reps
+    flop = 2.0 * 37440 * 512 * 512 * 64
+    return {"batch": 64, "image": [512, 512], "forward_ms": round(fwd, 3),
+            "backward_ms": round(ev[1].elapsed_time(ev[2]) / reps, 3),
+            "forward_tflops": round(flop / (fwd * 1e-3) / 1e12, 1)}
+
+
 def bench_blur_dct(torch, ops, lib, stream) -> dict:
     """R through the DCT-II (five passes, any radius) against the direct tile
     kernel (radius <= 12) at 2048^2, FP32, us per application (graph replay)."""
@@ -783,6 +814,9 @@ def main():
         return
     if args.only_conv:
         print(json.dumps(bench_conv(torch, ops)))
+        return
+    if args.only_cnn:
+        print(json.dumps(bench_cnn(torch)))
         return
     if args.only_dct:
         print(json.dumps(bench_blur_dct(torch, ops, _lib.load(), torch.cuda.Stream(device=dev))))
