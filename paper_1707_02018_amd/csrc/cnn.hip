@@ -135,9 +135,16 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
   const long long plane = (long long)H * W;
   const float* s = src + (long long)blockIdx.z * plane;
   const long long pbase = (long long)blockIdx.z * plane + x;
-  u32x4 wv[9];
+  float wf[9][8];  // the weights, widened once
 #pragma unroll
-  for (int t = 0; t < 9; ++t) wv[t] = ld16(w + t * 32 + 8 * g);
+  for (int t = 0; t < 9; ++t) {
+    const u32x4 wv = ld16(w + t * 32 + 8 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      wf[t][2 * j] = bf2f(wv[j] & 0xffffu);
+      wf[t][2 * j + 1] = bf2f(wv[j] >> 16);
+    }
+  }
   float b8[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) b8[j] = FWD ? bias[8 * g + j] : 0.0f;
@@ -149,14 +156,21 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
       v[k] = FWD ? u : rnd_bf(u);
     }
   };
-  float in[3][3];  // rows r - 1, r, r + 1
+  // rows r - 1, r, r + 1, and r + 2 (read one row ahead, with the next
+  // row's mask, so the loads are in flight during a row's arithmetic)
+  float in[4][3] = {};
   in_row(r0 - 1, in[0]);
   in_row(r0, in[1]);
+  in_row(r0 + 1, in[2]);
+  u32x4 mk_next = {0, 0, 0, 0};
+  if (!FWD && r0 < r1) mk_next = ld16(mask + (pbase + (long long)r0 * W) * 32 + 8 * g);
   for (int r = r0; r < r1; ++r) {
-    in_row(r + 1, in[2]);
     const long long p = pbase + (long long)r * W;
-    u32x4 mk = {0, 0, 0, 0};
-    if (!FWD) mk = ld16(mask + p * 32 + 8 * g);
+    const u32x4 mk = mk_next;
+    if (r + 1 < r1) {
+      in_row(r + 2, in[3]);
+      if (!FWD) mk_next = ld16(mask + (p + W) * 32 + 8 * g);
+    }
     float acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = b8[j];
@@ -164,10 +178,7 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
     for (int t = 0; t < 9; ++t) {
       const float iv = in[t / 3][t % 3];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[2 * j] += bf2f(wv[t][j] & 0xffffu) * iv;
-        acc[2 * j + 1] += bf2f(wv[t][j] >> 16) * iv;
-      }
+      for (int j = 0; j < 8; ++j) acc[j] += wf[t][j] * iv;
     }
     u32x4 out;
 #pragma unroll
@@ -187,6 +198,7 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
     for (int k = 0; k < 3; ++k) {
       in[0][k] = in[1][k];
       in[1][k] = in[2][k];
+      in[2][k] = in[3][k];
     }
   }
 }
@@ -273,11 +285,12 @@ __device__ __forceinline__ void lds_frags(Frags& F, const uint16_t* B, int pw, i
 // contiguous bytes and each store instruction writes 1 KB of the row: lane l
 // takes pixel 16 k + l / 4, channels 8 (l % 4) .. + 7 (k = 0, 1). The ReLU
 // mask of the input gradient is applied to the rounded values (a zero rounds
-// to zero), read with the same coalesced pattern.
+// to zero), read with the same coalesced pattern (mk, loaded by the caller
+// before the row's MFMAs).
 template <int MODE>
 __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, long long img_off,
                                               int o, int x, int h, uint16_t* ob, int xw,
-                                              const float* sbias) {
+                                              const float* sbias, const u32x4 (&mk)[2]) {
   if constexpr (MODE == kOut) {
     if (x < a.W && h == 0) {
       const long long pix = img_off + (long long)o * a.W + x;
@@ -315,11 +328,10 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, lo
       if (xw + p < a.W) {
         const long long pix = row + xw + p;
         if constexpr (MODE == kDgrad) {
-          const u32x4 mk = ld16(a.mask + pix * 32 + 8 * c);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            if (!bf_positive(mk[j] & 0xffffu)) v[j] &= 0xffff0000u;
-            if (!bf_positive(mk[j] >> 16)) v[j] &= 0x0000ffffu;
+            if (!bf_positive(mk[k][j] & 0xffffu)) v[j] &= 0xffff0000u;
+            if (!bf_positive(mk[k][j] >> 16)) v[j] &= 0x0000ffffu;
           }
         }
         *reinterpret_cast<u32x4*>(a.y + pix * 32 + 8 * c) = v;
@@ -354,6 +366,20 @@ __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, l
                                          u32x4 (&pre)[kConvLoads], f32x16& a0, f32x16& a1,
                                          f32x16& a2, int r, int y0, int yend, int x, int h, int pw,
                                          int xs, uint16_t* ob, const float* sbias) {
+  const int o = r - 1;
+  const bool emit = o >= y0 && o < yend;
+  u32x4 mk[2] = {};
+  if constexpr (MODE == kDgrad) {  // the epilogue's mask, in flight during the MFMAs
+    if (emit) {
+      const int lane = threadIdx.x & 63, xw = x - (threadIdx.x & 31);
+      const long long row = img_off + (long long)o * a.W;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int p = 16 * k + (lane >> 2);
+        if (xw + p < a.W) mk[k] = ld16(a.mask + (row + xw + p) * 32 + 8 * (lane & 3));
+      }
+    }
+  }
   Frags cur;
   lds_frags(cur, ring + S * kConvRowElems, pw, h);
   if (r + 2 <= yend) stage_store(ring + ((S + 2) % 3) * kConvRowElems, pre);
@@ -363,10 +389,8 @@ __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, l
     if (r >= y0 && r < yend) conv_taps<1>(wa, cur, pick<(S + 2) % 3>(a0, a1, a2));
     if (r - 1 >= y0 && r - 1 < yend) conv_taps<2>(wa, cur, pick<(S + 1) % 3>(a0, a1, a2));
   }
-  const int o = r - 1;
   f32x16& done = pick<(S + 1) % 3>(a0, a1, a2);
-  if (o >= y0 && o < yend)
-    conv_epilogue<MODE>(a, done, img_off, o, x, h, ob, x - (threadIdx.x & 31), sbias);
+  if (emit) conv_epilogue<MODE>(a, done, img_off, o, x, h, ob, x - (threadIdx.x & 31), sbias, mk);
   else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) done[i] = 0.0f;
@@ -459,7 +483,7 @@ __device__ __forceinline__ void put_pair(uint16_t* T, int pitch, int col, int g,
   }
 }
 
-__global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
+__global__ __launch_bounds__(256, 2) void wgrad32_kernel(WgradArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[kWgLds];
   uint16_t* dzT = lds;
   uint16_t* xT = lds + 32 * kWgPD;
@@ -494,10 +518,12 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
       put_pair(xT + s * 32 * kWgPY, kWgPY, 2 * q, gg, u0, u1);
     }
 
-  for (int o = y0; o < y1; ++o) {
-    const u32x4 d0 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp, g);
-    const u32x4 d1 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp + 1, g);
-    u32x4 e0[2], e1[2];
+  // dz row o and x row o + 1 into registers; issued one row ahead, so they
+  // are in flight during the previous row's MFMAs
+  u32x4 d0, d1, e0[2], e1[2];
+  auto fetch = [&](int o) {
+    d0 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp, g);
+    d1 = load_chunk(DZ, a.H, a.W, o, x0 + 2 * pp + 1, g);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int j = tid + 256 * k;
@@ -506,6 +532,9 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
       e0[k] = on ? load_chunk(XS, a.H, a.W, o + 1, c, gg) : u32x4{0, 0, 0, 0};
       e1[k] = on ? load_chunk(XS, a.H, a.W, o + 1, c + 1, gg) : u32x4{0, 0, 0, 0};
     }
+  };
+  if (y0 < y1) fetch(y0);
+  for (int o = y0; o < y1; ++o) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       bsum[2 * i] += bf2f(d0[i] & 0xffffu) + bf2f(d1[i] & 0xffffu);
@@ -521,6 +550,7 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
       if (j < kWgPairsY * 4) put_pair(xT + snew * 32 * kWgPY, kWgPY, 2 * (j >> 2), j & 3, e0[k], e1[k]);
     }
     __syncthreads();
+    if (o + 1 < y1) fetch(o + 1);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int k0 = (wv * 2 + c) * 16;
@@ -588,12 +618,14 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a) {
 // out[c][t] = sum_p X32[p][c] x1'[p + off(t)] (stored at c * 9 + (flip ? 8 - t : t)),
 // x1' = x1 for the input layer (the FP32 image), rnd(x1) for the output layer (a gradient);
 // out[288 + c] = sum_p X32[p][c] (width 320)  or  out[288] = sum_p x1[p] (width 289).
-constexpr int kWinPix = 4096;  // pixels per workgroup
+// One workgroup per 64 x 64 tile of an image, one partial row per workgroup.
+constexpr int kWinCols = 64, kWinRows = 64;  // workgroup tile: 64 columns x 64 rows
 
 __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restrict__ X32,
                                                        const float* __restrict__ x1,
                                                        float* __restrict__ part, int H, int W,
-                                                       long long npix, int flip, int width) {
+                                                       int tiles_x, int tiles_y, int flip,
+                                                       int width) {
   __shared__ float red[4][4][81];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = tid & 3;
   float acc[72], s32[8], s1 = 0.0f;
@@ -601,44 +633,47 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
   for (int i = 0; i < 72; ++i) acc[i] = 0.0f;
 #pragma unroll
   for (int j = 0; j < 8; ++j) s32[j] = 0.0f;
-  const long long p0 = (long long)blockIdx.x * kWinPix;
-  const long long p1 = min(p0 + kWinPix, npix);
-  // the thread's pixel as (image, row, column), divided once and then
-  // advanced by 64 pixels per iteration
-  long long p = p0 + (tid >> 2);
-  int x = (int)(p % W);
-  long long q = p / W;
-  int r = (int)(q % H);
-  long long im = q / H;
-  for (; p < p1; p += 64) {
-    const float* s = x1 + im * (long long)H * W;
-    float in[9];
+  // tile (column block, row block, image); the thread walks one pixel column
+  // (channel group g) down the tile's rows with a sliding 3 x 3 window of x1
+  const int tx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
+  const int ty = rest % tiles_y, im = rest / tiles_y;
+  const int x = tx * kWinCols + (tid >> 2);
+  const int r0 = ty * kWinRows, r1 = min(r0 + kWinRows, H);
+  if (x < W) {
+    const long long plane = (long long)H * W;
+    const float* s = x1 + (long long)im * plane;
+    const uint16_t* X = X32 + ((long long)im * plane + x) * 32 + 8 * g;
+    auto in_row = [&](int rr, float (&v)[3]) {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int rr = r + t / 3 - 1, cc = x + t % 3 - 1;
-      const float v = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
-      in[t] = flip ? rnd_bf(v) : v;
-    }
-    const u32x4 v = ld16(X32 + p * 32 + 8 * g);
-    float xv[8];
+      for (int k = 0; k < 3; ++k) {
+        const int cc = x + k - 1;
+        const float u = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? s[(long long)rr * W + cc] : 0.0f;
+        v[k] = flip ? rnd_bf(u) : u;
+      }
+    };
+    float in[3][3];  // x1 rows r - 1, r, r + 1 around column x
+    in_row(r0 - 1, in[0]);
+    in_row(r0, in[1]);
+    for (int r = r0; r < r1; ++r) {
+      const u32x4 v = ld16(X + (long long)r * W * 32);
+      in_row(r + 1, in[2]);
+      float xv[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      xv[2 * j] = bf2f(v[j] & 0xffffu);
-      xv[2 * j + 1] = bf2f(v[j] >> 16);
-    }
+      for (int j = 0; j < 4; ++j) {
+        xv[2 * j] = bf2f(v[j] & 0xffffu);
+        xv[2 * j + 1] = bf2f(v[j] >> 16);
+      }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      s32[j] += xv[j];
+      for (int j = 0; j < 8; ++j) {
+        s32[j] += xv[j];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t];
-    }
-    if (g == 0) s1 += s[(long long)r * W + x];
-    x += 64;
-    while (x >= W) {
-      x -= W;
-      if (++r == H) {
-        r = 0;
-        ++im;
+        for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t / 3][t % 3];
+      }
+      if (g == 0) s1 += s[(long long)r * W + x];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        in[0][k] = in[1][k];
+        in[1][k] = in[2][k];
       }
     }
   }
@@ -797,7 +832,7 @@ WgradPlan wgrad_plan(int n, int H, int W) {
 }
 
 long long win_blocks(int n, int H, int W) {
-  return ((long long)n * H * W + kWinPix - 1) / kWinPix;
+  return (long long)n * ((H + kWinRows - 1) / kWinRows) * ((W + kWinCols - 1) / kWinCols);
 }
 
 hipError_t col_sum(const float* part, int nrows, int width, double* tmp, float* out,
@@ -859,7 +894,6 @@ hipError_t launch_cnn_backward(const void* packed, int n, int H, int W, const fl
   const uint16_t* A = static_cast<const uint16_t*>(acts);
   uint16_t* D = static_cast<uint16_t*>(dacts);
   const long long layer = (long long)n * H * W * kCnnCh;
-  const long long npix = (long long)n * H * W;
   const WgradPlan wp = wgrad_plan(n, H, W);
   const long long wb = win_blocks(n, H, W);
   const long long rows = wp.nwg > wb ? wp.nwg : wb;
@@ -868,8 +902,9 @@ hipError_t launch_cnn_backward(const void* packed, int n, int H, int W, const fl
                                           ((size_t)rows * kWgWidth * sizeof(float) + 255) / 256 * 256);
   hipError_t e;
   // output layer: weights, then the gradient at layer 5's pre-activation
+  const int wtx = (W + kWinCols - 1) / kWinCols, wty = (H + kWinRows - 1) / kWinRows;
   hipLaunchKernelGGL(wgrad_in_kernel, dim3((unsigned)wb), dim3(256), 0, s, A + 4 * layer, du, part,
-                     H, W, npix, 1, 289);
+                     H, W, wtx, wty, 1, 289);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = col_sum(part, (int)wb, 289, tmp, grad + kCnnMasterW6, s)) != hipSuccess) return e;
   if ((e = launch_conv_in(false, du, reinterpret_cast<const uint16_t*>(pk + CnnPack::w6d), nullptr,
@@ -898,8 +933,8 @@ hipError_t launch_cnn_backward(const void* packed, int n, int H, int W, const fl
     if ((e = launch_conv32<kDgrad>(a, s)) != hipSuccess) return e;
   }
   // input layer: weights only (no gradient is needed at the image)
-  hipLaunchKernelGGL(wgrad_in_kernel, dim3((unsigned)wb), dim3(256), 0, s, D, b, part, H, W, npix, 0,
-                     320);
+  hipLaunchKernelGGL(wgrad_in_kernel, dim3((unsigned)wb), dim3(256), 0, s, D, b, part, H, W, wtx, wty,
+                     0, 320);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return col_sum(part, (int)wb, 320, tmp, grad + kCnnMasterW1, s);
 }
