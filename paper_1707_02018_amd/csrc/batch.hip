@@ -210,7 +210,7 @@ void layout(aw_batch* p) {
   int amax = 0;  // analysis-tile partial slots for either tile variant
   for (int i = 0; i < p->n; ++i) {
     int tx;
-    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
+    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2] == 1 ? 1 : 0, p->img[i].b, &tx);
     const Image& im = p->img[i];
     for (int j = 1; j <= im.J; ++j) {
       aw::AnaLevel d{};
@@ -263,6 +263,10 @@ void add_item(Group& g, const void* item, size_t sz, int tiles) {
   g.prefix.push_back(g.total);
 }
 
+// Blur tile variant: cfg value 1 half-height tiles; 0 and 2 full-height
+// tiles (2: one launch per blur stage, below).
+int blur_var(const aw_batch* p) { return p->var[2] == 1 ? 1 : 0; }
+
 // Analysis tile variant of level j: cfg value 2 takes full-height tiles for
 // the finest level (the large launches) and half-height ones for the coarser
 // levels (the short, latency-bound launches), as the single-image path does.
@@ -277,7 +281,7 @@ aw_status build(aw_batch* p) {
   // recompute residual-partial offsets for the current blur variant
   for (int i = 0; i < p->n; ++i) {
     int tx;
-    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, p->var[2], p->img[i].b, &tx);
+    p->r_off[i + 1] = p->r_off[i] + aw::blur_tiles_var(0, blur_var(p), p->img[i].b, &tx);
   }
   // analysis-tile partial slots for the current analysis variant
   for (int i = 0; i < p->n; ++i) {
@@ -321,23 +325,37 @@ aw_status build(aw_batch* p) {
     }
     p->stages.push_back(std::move(st));
   }
-  // R y - b and R^* r
+  // R y - b and R^* r. With cfg[2] = 2 every image joins one class at the
+  // largest radius of the batch, its PSF zero-padded to that radius: one
+  // launch per stage, and the same values (the padded taps add exact zeros;
+  // the R^* border correction of the padded taps is that of the PSF).
+  int rbig = 0;
+  for (const Image& im : p->img) rbig = std::max(rbig, im.b.radius);
   for (int adj = 0; adj < 2; ++adj) {
     Stage st;
     for (int i = 0; i < p->n; ++i) {
       const Image& im = p->img[i];
+      aw::BlurDesc bd = im.b;
+      if (p->var[2] == 2 && im.b.radius < rbig) {
+        const int r = im.b.radius;
+        bd.radius = rbig;
+        for (int k = 0; k < 2 * rbig + 1; ++k) {
+          const int u = k - (rbig - r);
+          bd.taps[k] = (u >= 0 && u < 2 * r + 1) ? im.b.taps[u] : 0.0;
+        }
+      }
       int tx;
-      const int tiles = aw::blur_tiles_var(0, p->var[2], im.b, &tx);
+      const int tiles = aw::blur_tiles_var(0, blur_var(p), bd, &tx);
       const float* bi = static_cast<const float*>(p->b_obs) + p->img_off[i];
       if (!adj)
-        aw::make_blur_item(0, false, im.b, ws + im.tmp_off, ws + im.res_off, bi, rpart + p->r_off[i],
+        aw::make_blur_item(0, false, bd, ws + im.tmp_off, ws + im.res_off, bi, rpart + p->r_off[i],
                            i, tx, buf.data());
       else
-        aw::make_blur_item(0, true, im.b, ws + im.res_off, ws + im.tmp_off, nullptr, nullptr, i, tx,
+        aw::make_blur_item(0, true, bd, ws + im.res_off, ws + im.tmp_off, nullptr, nullptr, i, tx,
                            buf.data());
-      Group& g = group_for(st, 2 + adj, im.b.radius, 0);
+      Group& g = group_for(st, 2 + adj, bd.radius, 0);
       add_item(g, buf.data(), aw::blur_item_size(0), tiles);
-      g.var = p->var[2];
+      g.var = blur_var(p);
     }
     p->stages.push_back(std::move(st));
   }
@@ -519,8 +537,8 @@ aw_status aw_batch_layout(const aw_batch* p, int64_t* coef_off, int64_t* img_off
 aw_status aw_batch_set_config(aw_batch* p, const int32_t* var) {
   if (!p || !var) return bfail(AW_EINVAL, "invalid arguments");
   for (int k = 0; k < 3; ++k)
-    if (var[k] != 0 && var[k] != 1 && !(k == 1 && var[k] == 2))
-      return bfail(AW_EINVAL, "tile variant must be 0 or 1 (analysis: 0, 1 or 2)");
+    if (var[k] != 0 && var[k] != 1 && !(k >= 1 && var[k] == 2))
+      return bfail(AW_EINVAL, "tile variant must be 0 or 1 (analysis and blur: 0, 1 or 2)");
   if (var[3] < 1 || var[3] > 4) return bfail(AW_EINVAL, "streams must be 1..4");
   for (int k = 0; k < 4; ++k) p->var[k] = var[k];
   if (p->bound) return build(p);

@@ -77,7 +77,8 @@ def test_graph_replay_and_variants_equal_eager(setup):
     bf.run(ITERS, graph=False)
     torch.cuda.synchronize()
     eager = bf.X.clone()
-    for cfg in [(0, 0, 0, 4), (1, 1, 1, 1), (0, 1, 0, 2), (1, 0, 1, 4), (0, 2, 0, 3)]:
+    for cfg in [(0, 0, 0, 4), (1, 1, 1, 1), (0, 1, 0, 2), (1, 0, 1, 4), (0, 2, 0, 3), (0, 2, 2, 4),
+                (1, 1, 2, 1)]:
         bf.set_config(cfg)
         bf.reset()
         bf.run(ITERS, graph=True)
@@ -88,6 +89,34 @@ def test_graph_replay_and_variants_equal_eager(setup):
         bf.run(ITERS, graph=True)
         torch.cuda.synchronize()
         assert torch.equal(bf.X, eager), cfg
+
+
+def test_one_launch_blur_stage_with_asymmetric_psfs():
+    """Blur variant 2 (every PSF zero-padded to the batch's largest radius,
+    one launch per blur stage) equals the per-radius launches bitwise, also
+    for asymmetric PSFs, whose R^* border correction the padding must keep."""
+    rng = rng_for(3, 40)
+    probs = [(48, 40, 2, 8, 3), (72, 96, 3, 2, 9), (33, 50, 2, 8, 0)]
+    specs, obs = [], []
+    for r, c, J, L, rad in probs:
+        img = gen_image(rng, r, c)
+        taps = rng.uniform(0.1, 1.0, 2 * rad + 1)
+        taps /= taps.sum()
+        b = obl.R(img, taps) + gen_noise(rng, img.shape)
+        specs.append((ops.WaveletSpec(r, c, J, lo=ofl.by_taps(L), bc="sym"),
+                      ops.BlurSpec(r, c, taps=taps)))
+        obs.append(torch.tensor(b, dtype=torch.float32, device=DEV))
+    bf = BatchedFista(specs, obs, LAM)
+    out = []
+    for cfg in [(0, 0, 0, 1), (0, 0, 2, 1), (0, 0, 2, 4)]:
+        bf.set_config(cfg)
+        bf.reset()
+        bf.run(ITERS, graph=False)
+        torch.cuda.synchronize()
+        out.append((bf.X.clone(), bf.obj.clone()))
+    for X, O in out[1:]:
+        assert torch.equal(X, out[0][0])
+        assert torch.equal(O, out[0][1])
 
 
 def test_inactive_problem_is_frozen(setup):
