@@ -191,6 +191,8 @@ def parse():
                     help="run only the uneven-batch section and print its JSON (for profiling)")
     ap.add_argument("--only-conv", action="store_true",
                     help="run only the convolution-pair section and print its JSON (for profiling)")
+    ap.add_argument("--only-autograd", action="store_true",
+                    help="run only the autograd A section and print its JSON (for profiling)")
     ap.add_argument("--only-cnn", action="store_true",
                     help="run only the warm-start CNN timing and print its JSON (for profiling)")
     ap.add_argument("--only-dct", action="store_true",
@@ -261,7 +263,10 @@ def bench_batched(torch, ops, iters: int) -> dict:
 
 def bench_autograd(torch, ops) -> dict:
     """A = R W as an autograd Function, batch 16 of 1024 x 1024 FP32 (db4 J=4
-    sym, sigma 2 PSF): forward + backward (backward = A^* kernel)."""
+    sym, sigma 2 PSF): forward + backward (backward = A^* kernel). The leaf's
+    gradient is set to None before each backward, as a training loop's
+    zero_grad(set_to_none=True) does, so backward writes it instead of adding
+    into it."""
     from paper_1707_02018_amd import autograd as ag
     dev = torch.device("cuda:0")
     w = ops.WaveletSpec(1024, 1024, 4, taps=8, bc="sym")
@@ -269,12 +274,14 @@ def bench_autograd(torch, ops) -> dict:
     x = torch.randn(16, w.ncoef, device=dev, requires_grad=True)
     g = torch.randn(16, 1024, 1024, device=dev)
     for _ in range(3):
+        x.grad = None
         ag.apply_A(x, w, b).backward(g)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
     e0.record()
     for _ in range(reps):
+        x.grad = None
         ag.apply_A(x, w, b).backward(g)
     e1.record()
     torch.cuda.synchronize()
@@ -814,6 +821,9 @@ def main():
         return
     if args.only_conv:
         print(json.dumps(bench_conv(torch, ops)))
+        return
+    if args.only_autograd:
+        print(json.dumps(bench_autograd(torch, ops)))
         return
     if args.only_cnn:
         print(json.dumps(bench_cnn(torch)))
