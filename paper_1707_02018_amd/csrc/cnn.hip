@@ -43,6 +43,16 @@ __device__ __forceinline__ unsigned f2bf(float f) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+// Two values rounded to nearest even and packed (lo in the low half) by one
+// v_cvt_pk_bf16_f32; equal to f2bf for every non-NaN input with FP32
+// denormals kept (the default; a NaN stays a quiet NaN).
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned f2bf2(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
+}
+
 __device__ __forceinline__ bool bf_positive(unsigned h) { return !(h & 0x8000u) && (h & 0x7fffu); }
 
 __device__ __forceinline__ float rnd_bf(float f) { return bf2f(f2bf(f)); }
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
         if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
         if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
       }
-      out[j] = f2bf(a0) | (f2bf(a1) << 16);
+      out[j] = f2bf2(a0, a1);
     }
     *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
 #pragma unroll
@@ -312,8 +322,8 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, lo
         v[3] = fmaxf(v[3] + bv.w, 0.0f);
       }
       u32x2 st;
-      st[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
-      st[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
+      st[0] = f2bf2(v[0], v[1]);
+      st[1] = f2bf2(v[2], v[3]);
       *reinterpret_cast<u32x2*>(ob + xl * kConvPitch + co) = st;
     }
     // the tile is private to the wave and LDS operations of a wave complete
