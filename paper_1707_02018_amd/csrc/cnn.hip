@@ -409,7 +409,7 @@ __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, l
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void conv32_kernel(ConvArgs a) {
+__global__ __launch_bounds__(256, MODE == kDgrad ? 2 : 1) void conv32_kernel(ConvArgs a) {
   __shared__ __align__(16) uint16_t ring[3 * kConvRowElems];
   __shared__ __align__(16) uint16_t obuf[4][32 * kConvPitch];  // per wave: one output row
   __shared__ __align__(16) float sbias[32];
