@@ -90,6 +90,11 @@ class BatchedFista:
     # ------------------------------------------------------------- control
     def __del__(self):
         try:
+            # the captured graph goes before the plan: the plan owns the
+            # auxiliary streams, events and device tables the graph was
+            # captured with
+            self._graph = None
+            self._graph_stream = None
             if getattr(self, "_plan", None) is not None and self._plan.value:
                 load().aw_batch_destroy(self._plan)
                 self._plan = None
@@ -102,9 +107,12 @@ class BatchedFista:
     def set_config(self, cfg) -> None:
         arr = (ctypes.c_int32 * 4)(*[int(v) for v in cfg])
         torch.cuda.synchronize(self.device)
+        # drop the graph first: rebuilding the plan frees the device tables
+        # its kernels were captured with
+        self._graph = None
+        self._graph_stream = None
         check("aw_batch_set_config", load().aw_batch_set_config(self._plan, arr))
         self.config = tuple(int(v) for v in cfg)
-        self._graph = None
 
     def reset(self) -> None:
         """k = 1, all problems active, x = y = 0."""
