@@ -239,7 +239,7 @@ aw::SynthLevel synth_desc(const WavePlan& p, aw_dtype dt, const void* coef, void
 aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* coef, void* img,
                         void* ws, const WsLayout& l, int pinv, hipStream_t s, int j_lo = 1) {
   const int dtype = dt == AW_F64;
-  // levels min(J, 4) .. 2 in one chained launch where supported
+  // levels min(J, 4) .. 2 in one chained launch where supported and faster
   int chain_top = 0;
   size_t chain_lds = 0;
   aw::SynthChain ch{};
@@ -248,7 +248,7 @@ aw_status run_synthesis(const WavePlan& p, aw_dtype dt, int batch, const void* c
     ch.nl = chain_top - 1;
     for (int k = 0; k < ch.nl; ++k) ch.d[k] = synth_desc(p, dt, coef, img, ws, l, pinv, 2 + k);
     chain_lds = aw::synth_chain_plan(dtype, p.L, ch);
-    if (!chain_lds) chain_top = 0;
+    if (!chain_lds || !aw::synth_chain_pays(ch, batch)) chain_top = 0;
   }
   for (int j = p.J; j >= j_lo; --j) {
     if (chain_top && j == chain_top) {

@@ -327,6 +327,10 @@ bool blur_ana_supported(int L, const AnaLevel& d, const BlurDesc& b);
 hipError_t launch_blur_ana(int L, const double* lo, const AnaLevel& d, const BlurDesc& b,
                            int batch, hipStream_t s);
 size_t synth_chain_plan(int dtype, int L, SynthChain& c);
+// Whether the chain beats one launch per level for this batch: its
+// workgroups (one per tile of a_1) recompute halos at about one workgroup per
+// CU, so past a few workgroups per CU the per-level kernels are faster.
+bool synth_chain_pays(const SynthChain& c, int batch);
 hipError_t launch_synth_chain(int L, const double* lo, const SynthChain& c, size_t lds, int batch,
                               hipStream_t s);
 // Analysis level with the fused FISTA update (see ProxEpi); tiles per image.

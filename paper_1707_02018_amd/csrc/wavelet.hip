@@ -258,6 +258,20 @@ size_t synth_chain_plan(int dtype, int L, SynthChain& c) {
   return lds <= 64 * 1024 ? lds : 0;
 }
 
+// Largest chain grid, in workgroups, that still beats the per-level launches
+// (2.5 per CU). Measured with db4, J = 4 (W, FP32): the chain is faster at
+// 297 workgroups (2048^2: 27.1 against 32.4 us) and 340 (4 x 1024^2),
+// level by level ties at 594-680 (2 x 2048^2, 8 x 1024^2) and wins from
+// about 1000 on (16 x 1024^2: 57.3 against 65.6 us, 4 x 4096^2: 183 against
+// 212 us).
+constexpr long long kChainMaxGrid = 640;
+
+bool synth_chain_pays(const SynthChain& c, int batch) {
+  const long long tiles = (long long)((c.d[0].c.N + kChainTC - 1) / kChainTC) *
+                          ((c.d[0].r.N + kChainTR - 1) / kChainTR);
+  return tiles * batch <= kChainMaxGrid;
+}
+
 template <int L, int BC>
 static hipError_t launch_chain_t(const double* lo, const SynthChain& c, size_t lds, int batch,
                                  hipStream_t s) {
