@@ -15,7 +15,8 @@
 // symmetric PSF (then R^* = R).
 //
 // A workgroup owns a TR x TC output tile and stages the reflected
-// (TR+2r) x (TC+2r) window in LDS: interior tiles with 16-byte loads, border
+// (TR+2r) x (TC+2r) window in LDS: interior tiles with 16-byte direct-to-LDS
+// loads (global_load_lds_dwordx4: no registers, no LDS write instructions), border
 // tiles through per-row / per-column reflection tables. The column pass writes
 // TR+2r rows of TC filtered values (VW outputs per thread from 16-byte LDS
 // reads); the row pass walks each column in chunks of four outputs. An optional
@@ -48,8 +49,10 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
   constexpr int TR = Cfg::TR, TC = Cfg::TC, VW = Cfg::VW, NT = Cfg::NT;
   constexpr int WR = TR + 2 * R;                       // window rows
   constexpr int WC = TC + 2 * R;                       // window cols
-  constexpr int SXS = ((WC + VW - 1) / VW) * VW + VW;  // sx row stride (vector aligned)
-  constexpr int NV = (VW + 2 * R + VW - 1) / VW;       // vectors read per column-pass item
+  constexpr int RA = ((R + VW - 1) / VW) * VW;         // aligned left halo
+  constexpr int OFF = RA - R;                          // sx column of window column 0
+  constexpr int SXS = TC + 2 * RA;                     // sx row: global columns c0-RA .. c0+TC+RA
+  constexpr int NV = (OFF + VW + 2 * R + VW - 1) / VW; // vectors read per column-pass item
   constexpr int K = 2 * R + 1;
   __shared__ __align__(16) T sx[WR * SXS];
   __shared__ __align__(16) T sh[WR * TC];
@@ -84,31 +87,24 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
   }
 
   // 1. stage the reflected window: rows r0-R .. r0+TR+R, cols c0-R .. c0+TC+R
-  constexpr int RA = ((R + VW - 1) / VW) * VW;  // aligned left halo
-  constexpr int WCV = (TC + 2 * RA) / VW;       // aligned vectors per window row
+  //    (sx holds the aligned columns c0-RA .. c0+TC+RA: window column j at
+  //    sx column j + OFF)
+  constexpr int WCV = SXS / VW;  // vectors per sx row
   if (interior && (M % VW) == 0) {
+    // interior: the 16-byte vectors go from memory straight to LDS, vector
+    // idx of sx (row-major, no padding) from lane idx % 64 of a wave
+    // instruction that writes 64 consecutive vectors
     constexpr int NVEC = WR * WCV;
     constexpr int IT = (NVEC + NT - 1) / NT;
-    V buf[IT];
+    const int wbase = threadIdx.x & ~63;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * NT;
       if (idx < NVEC) {
         const int i = idx / WCV, jv = idx - (idx / WCV) * WCV;
-        buf[it] = *reinterpret_cast<const V*>(Xi + (long long)(r0 - R + i) * M + (c0 - RA) + jv * VW);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NVEC) {
-        const int i = idx / WCV, jv = idx - (idx / WCV) * WCV;
-        const T* e = reinterpret_cast<const T*>(&buf[it]);
-#pragma unroll
-        for (int u = 0; u < VW; ++u) {
-          const int j = jv * VW + u - (RA - R);  // window column
-          if (j >= 0 && j < WC) sx[i * SXS + j] = e[u];
-        }
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void*>(Xi + (long long)(r0 - R + i) * M + (c0 - RA) + jv * VW),
+            (__attribute__((address_space(3))) void*)(sx + (wbase + it * NT) * VW), 16, 0, 0);
       }
     }
   } else {
@@ -130,13 +126,9 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
       const int idx = threadIdx.x + it * NT;
       if (idx < WR * WC) {
         const int i = idx / WC, j = idx - (idx / WC) * WC;
-        sx[i * SXS + j] = v[it];
+        sx[i * SXS + OFF + j] = v[it];
       }
     }
-  }
-  for (int idx = threadIdx.x; idx < WR * (SXS - WC); idx += NT) {  // vector padding
-    const int i = idx / (SXS - WC), j = idx - (idx / (SXS - WC)) * (SXS - WC);
-    sx[i * SXS + WC + j] = T(0);
   }
   __syncthreads();
 
@@ -148,7 +140,13 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
     T w[NV * VW];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const V vv = *reinterpret_cast<const V*>(row + v * VW);
+      using NV16 = T __attribute__((ext_vector_type(VW)));
+      NV16 vv = *reinterpret_cast<const NV16*>(row + v * VW);
+      // with the window off the vector grid (OFF > 0) the compiler would
+      // split the first and last 16-byte reads into narrower ones for the
+      // elements used; an empty asm that takes the whole vector keeps them
+      // single 16-byte reads
+      if constexpr (OFF > 0) asm volatile("" : "+v"(vv));
       const T* e = reinterpret_cast<const T*>(&vv);
 #pragma unroll
       for (int u = 0; u < VW; ++u) w[v * VW + u] = e[u];
@@ -159,7 +157,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
     for (int u = 0; u < VW; ++u) {
       T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc += t[k] * w[u + k];
+      for (int k = 0; k < K; ++k) acc += t[k] * w[OFF + u + k];
       o[u] = acc;
     }
     *reinterpret_cast<V*>(sh + i * TC + q * VW) = ov;
@@ -174,7 +172,8 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T>& a, const T* __restr
       T acc = T(0);
 #pragma unroll 1
       for (int k = 0; k < K; ++k)
-        if (refl_odd(p - R + k, M)) acc += (a.taps[K - 1 - k] - a.taps[k]) * sx[i * SXS + pc + k];
+        if (refl_odd(p - R + k, M))
+          acc += (a.taps[K - 1 - k] - a.taps[k]) * sx[i * SXS + OFF + pc + k];
       sh[i * TC + pc] += acc;
     }
   }
