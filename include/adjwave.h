@@ -357,6 +357,8 @@ aw_status aw_objective(const aw_wavelet* w, const aw_blur* b, aw_dtype dtype, in
 typedef struct aw_batch aw_batch;
 
 aw_status aw_batch_create(int32_t n, const aw_wavelet* w, const aw_blur* b, aw_batch** plan);
+/* Releases the plan and everything it owns; the plan is gone even when a
+ * runtime error is reported (AW_EHIP, the first error met). */
 aw_status aw_batch_destroy(aw_batch* plan);
 
 /* coef_off / img_off: n+1 element offsets of problem i in the concatenated

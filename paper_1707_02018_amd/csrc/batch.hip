@@ -415,8 +415,11 @@ aw_status build(aw_batch* p) {
   off = alignb(off + p->r_off.size() * sizeof(int));
   p->bpref_dev = off;
   off = alignb(off + p->blk_off.size() * sizeof(int));
-  if (p->blob) hipFree(p->blob);
-  p->blob = nullptr;
+  if (p->blob) {
+    const hipError_t fe = hipFree(p->blob);
+    p->blob = nullptr;
+    if (fe != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(fe));
+  }
   if (hipMalloc((void**)&p->blob, off) != hipSuccess) return bfail(AW_EHIP, "plan allocation failed");
   std::vector<unsigned char> host(off, 0);
   for (Stage& st : p->stages)
@@ -485,6 +488,21 @@ aw_status launch_group(aw_batch* p, const Group& g, hipStream_t s) {
   return AW_OK;
 }
 
+// Frees what the plan owns (tables, events, streams) and the plan; the first
+// runtime error, if any, is returned after everything has been released.
+hipError_t release(aw_batch* p) {
+  hipError_t first = hipSuccess;
+  auto keep = [&first](hipError_t e) {
+    if (first == hipSuccess && e != hipSuccess) first = e;
+  };
+  if (p->blob) keep(hipFree(p->blob));
+  for (hipEvent_t e : p->events) keep(hipEventDestroy(e));
+  for (int k = 0; k < 4; ++k)
+    if (p->aux[k]) keep(hipStreamDestroy(p->aux[k]));
+  delete p;
+  return first;
+}
+
 }  // namespace
 
 extern "C" {
@@ -505,7 +523,8 @@ aw_status aw_batch_create(int32_t n, const aw_wavelet* w, const aw_blur* b, aw_b
   layout(p);
   for (int k = 0; k < 4; ++k)
     if (hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking) != hipSuccess) {
-      delete p;
+      p->aux[k] = nullptr;
+      (void)release(p);  // the creation error is the one reported
       return bfail(AW_EHIP, "stream creation failed");
     }
   *plan = p;
@@ -515,11 +534,8 @@ aw_status aw_batch_create(int32_t n, const aw_wavelet* w, const aw_blur* b, aw_b
 
 aw_status aw_batch_destroy(aw_batch* p) {
   if (!p) return AW_OK;
-  if (p->blob) hipFree(p->blob);
-  for (hipEvent_t e : p->events) hipEventDestroy(e);
-  for (int k = 0; k < 4; ++k)
-    if (p->aux[k]) hipStreamDestroy(p->aux[k]);
-  delete p;
+  const hipError_t e = release(p);
+  if (e != hipSuccess) return bfail(AW_EHIP, hipGetErrorString(e));
   return AW_OK;
 }
 
