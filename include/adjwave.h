@@ -368,7 +368,8 @@ aw_status aw_batch_layout(const aw_batch* plan, int64_t* coef_off, int64_t* img_
 
 /* Tunables: cfg[0..2] tile-shape variant (0 full-height, 1 half-height
  * tiles) of the synthesis, analysis and blur kernels, the analysis also 2
- * (full height for the finest level, half height for the coarser ones), the
+ * (full height for the finest level, half height for the coarser ones) and
+ * 3 (half height for 16-tap filters, full height for the others), the
  * blur also 2 (full-height tiles, and one launch per blur stage: every PSF
  * zero-padded to the batch's largest radius, the same values as per-radius
  * launches);

@@ -195,7 +195,7 @@ class BatchedFista:
         self.set_config(best)
         best_ms = self.time_iters(iters)
         trials = [(tuple(best), best_ms)]
-        for k, choices in ((0, (0, 1)), (1, (0, 1, 2)), (2, (0, 1, 2)), (3, (1, 2, 4))):
+        for k, choices in ((0, (0, 1)), (1, (0, 1, 2, 3)), (2, (0, 1, 2)), (3, (1, 2, 4))):
             for v in choices:
                 if v == best[k]:
                     continue

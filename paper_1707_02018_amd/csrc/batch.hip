@@ -267,10 +267,19 @@ void add_item(Group& g, const void* item, size_t sz, int tiles) {
 // tiles (2: one launch per blur stage, below).
 int blur_var(const aw_batch* p) { return p->var[2] == 1 ? 1 : 0; }
 
-// Analysis tile variant of level j: cfg value 2 takes full-height tiles for
-// the finest level (the large launches) and half-height ones for the coarser
-// levels (the short, latency-bound launches), as the single-image path does.
-int ana_var(const aw_batch* p, int j) { return p->var[1] == 2 ? (j == 1 ? 0 : 1) : p->var[1]; }
+// Analysis tile variant of level j for filter length L: cfg value 2 takes
+// full-height tiles for the finest level (the large launches) and half-height
+// ones for the coarser levels (the short, latency-bound launches), as the
+// single-image path does; 3 takes half-height tiles for the 16-tap classes
+// (whose full-height tile with the fused update holds only two workgroups per
+// CU by its registers) and full-height tiles for the others.
+int ana_var(const aw_batch* p, int j, int L) {
+  switch (p->var[1]) {
+    case 2: return j == 1 ? 0 : 1;
+    case 3: return L == 16 ? 1 : 0;
+    default: return p->var[1];
+  }
+}
 
 aw_status build(aw_batch* p) {
   p->stages.clear();
@@ -291,7 +300,7 @@ aw_status build(aw_batch* p) {
       aw::AnaLevel d{};
       d.r = {im.sr[j - 1], im.sr[j], im.e};
       d.c = {im.sc[j - 1], im.sc[j], im.e};
-      t += aw::ana_tiles(0, ana_var(p, j), d);
+      t += aw::ana_tiles(0, ana_var(p, j, im.L), d);
     }
     p->blk_off[i + 1] = p->blk_off[i] + t;
   }
@@ -393,12 +402,12 @@ aw_status build(aw_batch* p) {
       pe.beta_tab = reinterpret_cast<const double*>(ws + p->beta_off);
       pe.counter = reinterpret_cast<const int*>(ws + p->ctr_off);
       pe.beta_len = kBetaLen;
-      const int tiles = aw::ana_tiles(0, ana_var(p, j), d);
+      const int tiles = aw::ana_tiles(0, ana_var(p, j, im.L), d);
       lvl_base[i] += tiles;
       aw::make_ana_item_prox(d, im.taps, im.L, i, pe, buf.data());
       Group& g = group_for(st, 1, im.L, im.bc);
       add_item(g, buf.data(), aw::ana_item_size(0), tiles);
-      g.var = ana_var(p, j);
+      g.var = ana_var(p, j, im.L);
     }
     p->stages.push_back(std::move(st));
   }
@@ -552,9 +561,10 @@ aw_status aw_batch_layout(const aw_batch* p, int64_t* coef_off, int64_t* img_off
 
 aw_status aw_batch_set_config(aw_batch* p, const int32_t* var) {
   if (!p || !var) return bfail(AW_EINVAL, "invalid arguments");
+  const int vmax[3] = {1, 3, 2};
   for (int k = 0; k < 3; ++k)
-    if (var[k] != 0 && var[k] != 1 && !(k >= 1 && var[k] == 2))
-      return bfail(AW_EINVAL, "tile variant must be 0 or 1 (analysis and blur: 0, 1 or 2)");
+    if (var[k] < 0 || var[k] > vmax[k])
+      return bfail(AW_EINVAL, "tile variant out of range (synthesis 0..1, analysis 0..3, blur 0..2)");
   if (var[3] < 1 || var[3] > 4) return bfail(AW_EINVAL, "streams must be 1..4");
   for (int k = 0; k < 4; ++k) p->var[k] = var[k];
   if (p->bound) return build(p);

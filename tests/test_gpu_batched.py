@@ -78,7 +78,7 @@ def test_graph_replay_and_variants_equal_eager(setup):
     torch.cuda.synchronize()
     eager = bf.X.clone()
     for cfg in [(0, 0, 0, 4), (1, 1, 1, 1), (0, 1, 0, 2), (1, 0, 1, 4), (0, 2, 0, 3), (0, 2, 2, 4),
-                (1, 1, 2, 1)]:
+                (1, 1, 2, 1), (0, 3, 0, 2), (1, 3, 1, 4)]:
         bf.set_config(cfg)
         bf.reset()
         bf.run(ITERS, graph=True)
@@ -158,3 +158,20 @@ def test_autotune_picks_a_valid_config(setup, tmp_path, monkeypatch):
     assert bf.config == tuple(rec["config"])
     rec2 = BatchedFista(specs, obs, LAM).autotune(iters=2)
     assert rec2["cached"] and rec2["config"] == rec["config"]
+
+
+def test_set_config_rejects_out_of_range_values(setup):
+    """Tile variants beyond synthesis 0..1, analysis 0..3, blur 0..2 and
+    stream counts beyond 1..4 fail with EINVAL and leave the plan as it was."""
+    from paper_1707_02018_amd._lib import AdjwaveError
+    specs, obs, _ = setup
+    bf = BatchedFista(specs, obs, LAM)
+    bf.set_config((0, 3, 0, 2))
+    for bad in [(2, 0, 0, 2), (0, 4, 0, 2), (0, 0, 3, 2), (-1, 0, 0, 2), (0, 0, 0, 0), (0, 0, 0, 5)]:
+        with pytest.raises(AdjwaveError):
+            bf.set_config(bad)
+    assert bf.config == (0, 3, 0, 2)
+    bf.reset()
+    bf.run(2, graph=False)
+    torch.cuda.synchronize()
+    assert int(bf.counter.item()) == 3
