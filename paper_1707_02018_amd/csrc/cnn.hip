@@ -225,10 +225,20 @@ struct ConvArgs {
   const float* base;     // [n][H][W] (kOut): added to output channel 0
   float* out;            // [n][H][W] (kOut)
   int n, H, W, strips, bands, groups;  // groups: workgroups per band (kConvStrips strips each)
+  int rows;                            // output rows per band (one of kConvRows)
 };
 
-constexpr int kConvR = 16;  // output rows per wave; (kConvR + 2) % 3 == 0
-static_assert((kConvR + 2) % 3 == 0, "row loop is unrolled by three");
+// Output rows per band (per workgroup), tallest first; the host takes the
+// tallest that still gives the grid kConvMinGrid workgroups (eight per CU),
+// the shortest otherwise. A taller band stages fewer halo rows per output
+// row and starts fewer workgroups: at 64 images of 512^2 the forward pass
+// measured 2.81 ms at 16 rows, 2.63 at 31, 2.58-2.60 at 64 (the backward
+// 7.03, 6.90, 6.81-6.87), 2.83 at 85 (too few workgroups); outputs are the
+// same for every height (each output row sums its three input rows in the
+// same order). Any height works with the row loop unrolled by three: rows
+// past the band's end skip their loads, taps and stores.
+constexpr int kConvRows[3] = {64, 31, 16};
+constexpr long long kConvMinGrid = 2048;
 
 struct Frags {
   u32x4 f[3][2];  // [kx][k half]
@@ -424,8 +434,8 @@ __global__ __launch_bounds__(256, MODE == kDgrad ? 2 : 1) void conv32_kernel(Con
   const int pw = w * 32 + (lane & 31);
   const int x = sg * 32 * kConvStrips + pw;  // beyond W for strips past the image: no stores
   const int xs = sg * 32 * kConvStrips - 1;  // first staged pixel
-  const int y0 = band * kConvR;
-  const int yend = min(y0 + kConvR, a.H);
+  const int y0 = band * a.rows;
+  const int yend = min(y0 + a.rows, a.H);
   const long long img_off = (long long)img * a.H * a.W;
   const uint16_t* X = a.x + img_off * 32;
 
@@ -799,9 +809,13 @@ ConvArgs conv_args(int n, int H, int W) {
   a.H = H;
   a.W = W;
   a.strips = (W + 31) / 32;
-  a.bands = (H + kConvR - 1) / kConvR;
   a.groups = (a.strips + kConvStrips - 1) / kConvStrips;
   a.n = n;
+  for (int rows : kConvRows) {
+    a.rows = rows;
+    a.bands = (H + rows - 1) / rows;
+    if ((long long)n * a.bands * a.groups >= kConvMinGrid) break;
+  }
   return a;
 }
 

@@ -179,6 +179,31 @@ def test_backward_is_deterministic():
     assert torch.equal(g1, g2) and torch.equal(d1, d2)
 
 
+def test_band_height_does_not_change_results():
+    """64 images of 512^2 run the 32-channel layers in 64-row bands (the grid
+    then has 2048 workgroups), one image alone in 16-row bands: activations,
+    output and input gradients of sampled images are bitwise the same (every
+    output row sums its three input rows in the same order)."""
+    theta, _, _ = make((1, 1, 1), 4)
+    net = Net(theta)
+    gen = torch.Generator(device=DEV).manual_seed(4)
+    n, H, W = 64, 512, 512
+    b = torch.rand(n, H, W, device=DEV, generator=gen)
+    du = torch.randn(n, H, W, device=DEV, generator=gen)
+    u, acts = net.forward(b)
+    _, dacts = net.backward(b, acts, du)
+    A = acts.view(torch.bfloat16).view(5, n, H, W, 32)
+    D = dacts.view(torch.bfloat16).view(5, n, H, W, 32)
+    for i in (0, 37, 63):
+        bi, dui = b[i:i + 1].contiguous(), du[i:i + 1].contiguous()
+        ui, ai = net.forward(bi)
+        _, di = net.backward(bi, ai, dui)
+        torch.cuda.synchronize()
+        assert torch.equal(u[i], ui[0]), i
+        assert torch.equal(A[:, i], ai.view(torch.bfloat16).view(5, 1, H, W, 32)[:, 0]), i
+        assert torch.equal(D[:, i], di.view(torch.bfloat16).view(5, 1, H, W, 32)[:, 0]), i
+
+
 def test_whole_network_close_to_fp64_oracle():
     """BF16 rounding of weights and activations against the unrounded FP64
     network: a loose sanity bound (rounding compounds over six layers)."""
