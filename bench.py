@@ -195,6 +195,10 @@ def parse():
                     help="run only the autograd A section and print its JSON (for profiling)")
     ap.add_argument("--only-cnn", action="store_true",
                     help="run only the warm-start CNN timing and print its JSON (for profiling)")
+    ap.add_argument("--only-large", action="store_true",
+                    help="level-1 W, W*, R, R* and update at 4 x 4096^2, streaming from HBM")
+    ap.add_argument("--large-summary", nargs=3, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="per-kernel table of --only-large --copy-reference runs")
     ap.add_argument("--only-dct", action="store_true",
                     help="run only the DCT-II blur section and print its JSON (for profiling)")
     ap.add_argument("--warm-images", type=int, default=16)
@@ -259,6 +263,131 @@ def bench_batched(torch, ops, iters: int) -> dict:
             "mpix_iter_per_s": round(npix / (ms * 1e-3) / 1e6, 1),
             "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
             "autotune": {"config": tune["config"], "trials": tune["trials"]}}
+
+
+LARGE_N, LARGE_BATCH, LARGE_SETS, LARGE_ROUNDS = 4096, 4, 3, 5
+LARGE_OPS = ["W_level1", "W*_level1", "R", "R*", "W*prox_level1"]
+
+
+def large_bytes(ops) -> dict:
+    """Algorithmic bytes per launch of the level-1 operators on 4 x 4096^2
+    (db4, sym, one level): inputs read once, outputs written once (FP32)."""
+    w1 = ops.WaveletSpec(LARGE_N, LARGE_N, 1, taps=8, bc="sym")
+    _, sr, sc = w1.layout()
+    npix, k1 = LARGE_N * LARGE_N, sr[1] * sc[1]
+    b = LARGE_BATCH
+    return {"W_level1": 4 * b * (w1.ncoef + npix), "W*_level1": 4 * b * (npix + w1.ncoef),
+            "R": 8 * b * npix, "R*": 8 * b * npix, "W*prox_level1": 4 * b * (npix + 16 * k1)}
+
+
+def bench_large(torch, ops) -> dict:
+    """Level-1 synthesis, analysis (W^*), R, R^* (radius 7) and the level-1
+    FISTA update on 4 x 4096^2 FP32 (db4, sym), each launch streaming from HBM:
+    inputs and outputs rotated over LARGE_SETS buffer sets of about 1.3 GB,
+    LARGE_ROUNDS rounds after one untimed round, HIP events on the stream."""
+    import ctypes
+    from paper_1707_02018_amd import _lib
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    N, B = LARGE_N, LARGE_BATCH
+    w1 = ops.WaveletSpec(N, N, 1, taps=8, bc="sym")
+    bsp = ops.BlurSpec(N, N, sigma=3.0, radius=7)
+    stream = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    P = ops._ptr
+    wsn = ops.workspace_bytes(w1, bsp, torch.float32, B)
+    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=dev)
+    g = torch.Generator(device=dev).manual_seed(5)
+    sets = []
+    for _ in range(LARGE_SETS):
+        st = _lib.FistaState()
+        x = torch.randn(B, w1.ncoef, device=dev, generator=g) * 1e-2
+        y = torch.randn(B, w1.ncoef, device=dev, generator=g) * 1e-2
+        st.x, st.y, st.resid, st.obj = x.data_ptr(), y.data_ptr(), None, None
+        st.k, st.t, st.gradient = 1, 1.0, 0
+        sets.append({"coef": torch.randn(B, w1.ncoef, device=dev, generator=g) * 1e-2,
+                     "img": torch.randn(B, N, N, device=dev, generator=g),
+                     "oimg": torch.empty(B, N, N, device=dev),
+                     "ocoef": torch.empty(B, w1.ncoef, device=dev), "x": x, "y": y, "st": st})
+    calls = {
+        "W_level1": lambda s: lib.wavelet_synth(w1.c, 0, B, P(s["coef"]), P(s["oimg"]), P(ws),
+                                                wsn, sp),
+        "W*_level1": lambda s: lib.wavelet_synth_adjoint(w1.c, 0, B, P(s["img"]), P(s["ocoef"]),
+                                                         P(ws), wsn, sp),
+        "R": lambda s: lib.blur(bsp.c, 0, B, P(s["img"]), P(s["oimg"]), sp),
+        "R*": lambda s: lib.blur_adjoint(bsp.c, 0, B, P(s["img"]), P(s["oimg"]), sp),
+        "W*prox_level1": lambda s: lib.aw_fista_update(w1.c, 0, B, P(s["img"]), 1.0, 2e-5,
+                                                       ctypes.byref(s["st"]), 0, P(ws), wsn, sp),
+    }
+    byts = large_bytes(ops)
+    out = {}
+    for name in LARGE_OPS:
+        fn = calls[name]
+        for s_ in sets:
+            assert fn(s_) == 0, name
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(LARGE_ROUNDS):
+            for s_ in sets:
+                fn(s_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / (LARGE_ROUNDS * LARGE_SETS)
+        out[name] = {"us": round(us, 2), "GBps": round(byts[name] / us / 1e3, 1),
+                     "frac": round(byts[name] / us / 1e6 / 8.0, 4)}
+    return {"workload": f"{B}x{N}^2 FP32, db4 sym, one level, PSF radius 7",
+            "cache": "each launch streams from HBM (buffer sets rotated)", "ops": out}
+
+
+def large_summary(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
+    """Per-kernel table of a `--only-large --copy-reference` run: average
+    duration from a rocprofv3 kernel trace, HBM bytes from FETCH_SIZE and
+    WRITE_SIZE passes scaled by the copy kernel's counters, against the
+    algorithmic bytes."""
+    import csv
+
+    from paper_1707_02018_amd import ops
+
+    def launches(path):
+        rows = [r for r in csv.DictReader(open(path)) if "aw::" in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    per = LARGE_SETS * (LARGE_ROUNDS + 1)
+    trace = launches(trace_csv)
+    if len(trace) != per * len(LARGE_OPS):
+        raise SystemExit(f"expected {per * len(LARGE_OPS)} launches, found {len(trace)}")
+
+    def factor(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        ref = [float(r["Counter_Value"]) for r in rows
+               if "elementwise" in r["Kernel_Name"] and int(r["Grid_Size"]) == COPY_REF_BYTES // 16]
+        return (COPY_REF_BYTES / 1024) / (sum(ref) / len(ref))
+
+    def counts(path, counter):
+        rows = [r for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and "aw::" in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [float(r["Counter_Value"]) for r in rows]
+
+    ff, wf = factor(fetch_csv, "FETCH_SIZE"), factor(write_csv, "WRITE_SIZE")
+    fk, wk = counts(fetch_csv, "FETCH_SIZE"), counts(write_csv, "WRITE_SIZE")
+    byts = large_bytes(ops)
+    print("| op | kernel | avg us | algorithmic MB | TB/s | of 8 TB/s | HBM MB (fetch + write) "
+          "| HBM / algorithmic |")
+    print("|---|---|---|---|---|---|---|---|")
+    for k, name in enumerate(LARGE_OPS):
+        sel = slice(k * per + LARGE_SETS, (k + 1) * per)  # the timed rounds
+        rows = trace[sel]
+        us = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows) / len(rows) / 1e3
+        hbm = 1024 * (ff * sum(fk[sel]) + wf * sum(wk[sel])) / len(rows)
+        kern = rows[0]["Kernel_Name"].split("(")[0].replace("void ", "")
+        print(f"| {name} | `{kern}` | {us:.1f} | {byts[name] / 1e6:.1f} | "
+              f"{byts[name] / us / 1e6:.2f} | {100 * byts[name] / us / 8e6:.1f} % | "
+              f"{hbm / 1e6:.1f} | {hbm / byts[name]:.2f} |")
+    print(f"\nFETCH_SIZE calibration {ff:.4f}, WRITE_SIZE {wf:.4f} (bytes of the "
+          f"{COPY_REF_BYTES >> 20} MiB copy over the KiB counted).")
 
 
 def bench_autograd(torch, ops) -> dict:
@@ -800,6 +929,9 @@ def main():
     if args.trace_summary:
         trace_summary(args.trace_summary[0], int(args.trace_summary[1]), args.size)
         return
+    if args.large_summary:
+        large_summary(*args.large_summary)
+        return
     if args.cpu_leg:
         print(json.dumps(cpu_leg(args.size, args.bc)))
         return
@@ -838,6 +970,9 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_large:
+        print(json.dumps(bench_large(torch, ops)))
+        return
     N, J, lam = args.size, 4, 2e-5
     w = ops.WaveletSpec(N, N, J, taps=8, bc=args.bc)
     bsp = ops.BlurSpec(N, N, sigma=3.0, radius=7)
