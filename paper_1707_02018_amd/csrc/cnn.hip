@@ -127,6 +127,7 @@ constexpr int kPackJobs = 288 + 32 + 4 * (2 * 9216 + 32) + 9216 + 32 + 288;
 // off(t) = (t / 3 - 1, t % 3 - 1). No thread divides a pixel index.
 // The image keeps FP32: its noise (1e-3) is below the BF16 step near 1 (2^-8).
 constexpr int kInRows = 16;  // output rows per thread
+constexpr int kInAhead = 4;  // rows of loads in flight per thread
 
 template <bool FWD>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ src,
@@ -166,49 +167,74 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
       v[k] = FWD ? u : rnd_bf(u);
     }
   };
-  // rows r - 1, r, r + 1, and r + 2 (read one row ahead, with the next
-  // row's mask, so the loads are in flight during a row's arithmetic)
-  float in[4][3] = {};
-  in_row(r0 - 1, in[0]);
-  in_row(r0, in[1]);
-  in_row(r0 + 1, in[2]);
-  u32x4 mk_next = {0, 0, 0, 0};
-  if (!FWD && r0 < r1) mk_next = ld16(mask + (pbase + (long long)r0 * W) * 32 + 8 * g);
-  for (int r = r0; r < r1; ++r) {
-    const long long p = pbase + (long long)r * W;
-    const u32x4 mk = mk_next;
-    if (r + 1 < r1) {
-      in_row(r + 2, in[3]);
-      if (!FWD) mk_next = ld16(mask + (p + W) * 32 + 8 * g);
-    }
-    float acc[8];
+  // The input row below each output row and the output row's mask are
+  // loaded kInAhead rows ahead of their use in a register ring, issued
+  // unconditionally from clamped addresses with the bounds applied when a
+  // value is used (a load under a condition would be waited for at once).
+  auto raw_row = [&](int rr, float (&v)[3]) {
+    const int rc = min(max(rr, 0), H - 1);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = b8[j];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const float iv = in[t / 3][t % 3];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] += wf[t][j] * iv;
-    }
-    u32x4 out;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float a0 = acc[2 * j], a1 = acc[2 * j + 1];
-      if (FWD) {
-        a0 = fmaxf(a0, 0.0f);
-        a1 = fmaxf(a1, 0.0f);
-      } else {
-        if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
-        if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
-      }
-      out[j] = f2bf2(a0, a1);
-    }
-    *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
+    for (int k = 0; k < 3; ++k) v[k] = s[(long long)rc * W + min(max(x + k - 1, 0), W - 1)];
+  };
+  auto use_row = [&](int rr, const float (&raw)[3], float (&v)[3]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      in[0][k] = in[1][k];
-      in[1][k] = in[2][k];
-      in[2][k] = in[3][k];
+      const int cc = x + k - 1;
+      const float u = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? raw[k] : 0.0f;
+      v[k] = FWD ? u : rnd_bf(u);
+    }
+  };
+  float in[3][3];  // rows r - 1, r, r + 1
+  in_row(r0 - 1, in[0]);
+  in_row(r0, in[1]);
+  float qr[kInAhead][3];
+  u32x4 qm[kInAhead];
+#pragma unroll
+  for (int d = 0; d < kInAhead; ++d) {
+    raw_row(r0 + d + 1, qr[d]);
+    qm[d] = FWD ? u32x4{0, 0, 0, 0}
+                : ld16(mask + (pbase + (long long)min(r0 + d, r1 - 1) * W) * 32 + 8 * g);
+  }
+  for (int r4 = r0; r4 < r1; r4 += kInAhead) {
+#pragma unroll
+    for (int d = 0; d < kInAhead; ++d) {
+      const int r = r4 + d;
+      const float raw[3] = {qr[d][0], qr[d][1], qr[d][2]};
+      const u32x4 mk = qm[d];
+      const int rn = r + kInAhead;
+      raw_row(rn + 1, qr[d]);
+      if (!FWD) qm[d] = ld16(mask + (pbase + (long long)min(rn, r1 - 1) * W) * 32 + 8 * g);
+      if (r >= r1) continue;
+      use_row(r + 1, raw, in[2]);
+      const long long p = pbase + (long long)r * W;
+      float acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = b8[j];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const float iv = in[t / 3][t % 3];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += wf[t][j] * iv;
+      }
+      u32x4 out;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float a0 = acc[2 * j], a1 = acc[2 * j + 1];
+        if (FWD) {
+          a0 = fmaxf(a0, 0.0f);
+          a1 = fmaxf(a1, 0.0f);
+        } else {
+          if (!bf_positive(mk[j] & 0xffffu)) a0 = 0.0f;
+          if (!bf_positive(mk[j] >> 16)) a1 = 0.0f;
+        }
+        out[j] = f2bf2(a0, a1);
+      }
+      *reinterpret_cast<u32x4*>(y + p * 32 + 8 * g) = out;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        in[0][k] = in[1][k];
+        in[1][k] = in[2][k];
+      }
     }
   }
 }
@@ -640,6 +666,7 @@ __global__ __launch_bounds__(256, 2) void wgrad32_kernel(WgradArgs a) {
 // out[288 + c] = sum_p X32[p][c] (width 320)  or  out[288] = sum_p x1[p] (width 289).
 // One workgroup per 64 x 64 tile of an image, one partial row per workgroup.
 constexpr int kWinCols = 64, kWinRows = 64;  // workgroup tile: 64 columns x 64 rows
+constexpr int kWinAhead = 4;                  // rows of loads in flight per thread
 
 __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restrict__ X32,
                                                        const float* __restrict__ x1,
@@ -671,29 +698,68 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
         v[k] = flip ? rnd_bf(u) : u;
       }
     };
+    // Loads run kWinAhead rows ahead of their use in a register ring (the
+    // layer input's 16-byte chunk, three x1 values, the centre value). They
+    // are issued unconditionally from clamped addresses, with the bounds
+    // applied when a value is used: a load under a condition would be waited
+    // for at once.
+    auto raw_row = [&](int rr, float (&v)[3]) {
+      const int rc = min(max(rr, 0), H - 1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[k] = s[(long long)rc * W + min(max(x + k - 1, 0), W - 1)];
+    };
+    auto use_row = [&](int rr, const float (&raw)[3], float (&v)[3]) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int cc = x + k - 1;
+        const float u = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? raw[k] : 0.0f;
+        v[k] = flip ? rnd_bf(u) : u;
+      }
+    };
     float in[3][3];  // x1 rows r - 1, r, r + 1 around column x
     in_row(r0 - 1, in[0]);
     in_row(r0, in[1]);
-    for (int r = r0; r < r1; ++r) {
-      const u32x4 v = ld16(X + (long long)r * W * 32);
-      in_row(r + 1, in[2]);
-      float xv[8];
+    u32x4 qx[kWinAhead];
+    float qr[kWinAhead][3], qs[kWinAhead];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        xv[2 * j] = bf2f(v[j] & 0xffffu);
-        xv[2 * j + 1] = bf2f(v[j] >> 16);
-      }
+    for (int d = 0; d < kWinAhead; ++d) {
+      const int rr = r0 + d;
+      qx[d] = ld16(X + (long long)min(rr, r1 - 1) * W * 32);
+      raw_row(rr + 1, qr[d]);
+      qs[d] = s[(long long)min(rr, H - 1) * W + x];
+    }
+    for (int r = r0; r < r1; r += kWinAhead) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        s32[j] += xv[j];
+      for (int d = 0; d < kWinAhead; ++d) {
+        const int rr = r + d;
+        const u32x4 v = qx[d];
+        const float raw[3] = {qr[d][0], qr[d][1], qr[d][2]};
+        const float sv = qs[d];
+        const int rn = rr + kWinAhead;
+        qx[d] = ld16(X + (long long)min(rn, r1 - 1) * W * 32);
+        raw_row(rn + 1, qr[d]);
+        qs[d] = s[(long long)min(rn, H - 1) * W + x];
+        if (rr < r1) {
+          use_row(rr + 1, raw, in[2]);
+          float xv[8];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t / 3][t % 3];
-      }
-      if (g == 0) s1 += s[(long long)r * W + x];
+          for (int j = 0; j < 4; ++j) {
+            xv[2 * j] = bf2f(v[j] & 0xffffu);
+            xv[2 * j + 1] = bf2f(v[j] >> 16);
+          }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        in[0][k] = in[1][k];
-        in[1][k] = in[2][k];
+          for (int j = 0; j < 8; ++j) {
+            s32[j] += xv[j];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[j * 9 + t] += xv[j] * in[t / 3][t % 3];
+          }
+          if (g == 0) s1 += sv;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            in[0][k] = in[1][k];
+            in[1][k] = in[2][k];
+          }
+        }
       }
     }
   }
