@@ -1,7 +1,6 @@
 // Warm-start CNN on gfx950: BF16 operands, FP32 accumulation.
 //
-// The 32 -> 32 layers (and the 32 -> 1 output layer, zero-padded to 32
-// outputs) are implicit GEMMs on v_mfma_f32_32x32x16_bf16 with M = 32 output
+// The 32 -> 32 layers are implicit GEMMs on v_mfma_f32_32x32x16_bf16 with M = 32 output
 // channels, N = 32 pixels of one image row, K = 16 input channels per tap half.
 // Each wave owns a 32-pixel column strip and slides down its rows: one input
 // row's three shifted fragments feed the three output rows that need them, so
@@ -18,7 +17,8 @@
 // tap shifts come from one aligned 16-byte read plus byte alignment.
 //
 // The 1 -> 32 input layer and the 32 -> 1 input gradient are VALU (nine
-// products per output), as is the weight gradient of those two layers.
+// products per output), as is the weight gradient of those two layers; the
+// 32 -> 1 output layer is VALU on BF16 pair dot products (v_dot2c_f32_bf16).
 // Every reduction is fixed-order: results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
@@ -239,17 +239,106 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
   }
 }
 
+// ------------------------------------------------------- 32 -> 1 (VALU)
+// u[p] = base[p] + bias + sum_t sum_c w[t][c] a[p + off(t)][c]: one output
+// channel, so the MFMA tile of the 32 -> 32 layers would compute 31 zero rows.
+// Four lanes (channel groups g of 8) share a pixel column and walk kInRows
+// rows with a 3 x 3 window of 16-byte chunks in registers; the next rows'
+// chunks are loaded kInAhead rows ahead, unconditionally from clamped
+// positions, with the bounds applied at use. The four partial sums of a
+// pixel are added across the lanes in a fixed order.
+__global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restrict__ X,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       const float* __restrict__ base,
+                                                       float* __restrict__ out, int H, int W) {
+  const int gx = blockIdx.x * 256 + threadIdx.x;
+  const int x = gx >> 2, g = gx & 3;
+  if (x >= W) return;  // the four lanes of a pixel column leave together
+  const int r0 = blockIdx.y * kInRows;
+  const int r1 = min(r0 + kInRows, H);
+  const long long plane = (long long)H * W;
+  const uint16_t* Xi = X + (long long)blockIdx.z * plane * 32 + 8 * g;
+  const long long obase = (long long)blockIdx.z * plane + x;
+  u32x4 wp[9];  // w[t][0][c]: output channel 0, channel pairs packed as BF16
+#pragma unroll
+  for (int t = 0; t < 9; ++t) wp[t] = ld16(w + t * 1024 + 8 * g);
+  const float b0 = bias[0];
+  auto raw_row = [&](int rr, u32x4 (&v)[3]) {
+    const int rc = min(max(rr, 0), H - 1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      v[k] = ld16(Xi + ((long long)rc * W + min(max(x + k - 1, 0), W - 1)) * 32);
+  };
+  auto use_row = [&](int rr, const u32x4 (&raw)[3], u32x4 (&v)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int cc = x + k - 1;
+      const bool ok = rr >= 0 && rr < H && cc >= 0 && cc < W;
+      v[k] = ok ? raw[k] : u32x4{0, 0, 0, 0};
+    }
+  };
+  u32x4 win[3][3];  // rows r - 1, r, r + 1; columns x - 1, x, x + 1
+  {
+    u32x4 raw[3];
+    raw_row(r0 - 1, raw);
+    use_row(r0 - 1, raw, win[0]);
+    raw_row(r0, raw);
+    use_row(r0, raw, win[1]);
+  }
+  u32x4 q[kInAhead][3];
+  float qb[kInAhead];
+#pragma unroll
+  for (int d = 0; d < kInAhead; ++d) {
+    raw_row(r0 + d + 1, q[d]);
+    qb[d] = base[obase + (long long)min(r0 + d, H - 1) * W];
+  }
+  for (int r4 = r0; r4 < r1; r4 += kInAhead) {
+#pragma unroll
+    for (int d = 0; d < kInAhead; ++d) {
+      const int r = r4 + d;
+      const u32x4 raw[3] = {q[d][0], q[d][1], q[d][2]};
+      const float bv = qb[d];
+      const int rn = r + kInAhead;
+      raw_row(rn + 1, q[d]);
+      qb[d] = base[obase + (long long)min(rn, H - 1) * W];
+      if (r >= r1) continue;
+      use_row(r + 1, raw, win[2]);
+      // BF16 pair dot products accumulated in FP32 (v_dot2c_f32_bf16)
+      float acc = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const u32x4 v = win[t / 3][t % 3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // each element copied out first: a bit cast of the vector element
+          // itself read element 0 every time
+          const unsigned vj = v[j], wj = wp[t][j];
+          acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, vj),
+                                                __builtin_bit_cast(bf16x2_t, wj), acc, false);
+        }
+      }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (g == 0) out[obase + (long long)r * W] = acc + b0 + bv;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        win[0][k] = win[1][k];
+        win[1][k] = win[2][k];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------- 32 -> 32 (MFMA)
-enum ConvMode { kFwd = 0, kDgrad = 1, kOut = 2 };
+enum ConvMode { kFwd = 0, kDgrad = 1 };
 
 struct ConvArgs {
   const uint16_t* x;     // [n][H][W][32]
   const uint16_t* w;     // [9][32 out][32 in]
-  const float* bias;     // [32] (kFwd, kOut)
+  const float* bias;     // [32] (kFwd)
   const uint16_t* mask;  // [n][H][W][32] (kDgrad)
   uint16_t* y;           // [n][H][W][32] (kFwd, kDgrad)
-  const float* base;     // [n][H][W] (kOut): added to output channel 0
-  float* out;            // [n][H][W] (kOut)
   int n, H, W, strips, bands, groups;  // groups: workgroups per band (kConvStrips strips each)
   int rows;                            // output rows per band (one of kConvRows)
 };
@@ -335,56 +424,49 @@ __device__ __forceinline__ void lds_frags(Frags& F, const uint16_t* B, int pw, i
 // before the row's MFMAs).
 template <int MODE>
 __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, f32x16& acc, long long img_off,
-                                              int o, int x, int h, uint16_t* ob, int xw,
+                                              int o, int h, uint16_t* ob, int xw,
                                               const float* sbias, const u32x4 (&mk)[2]) {
-  if constexpr (MODE == kOut) {
-    if (x < a.W && h == 0) {
-      const long long pix = img_off + (long long)o * a.W + x;
-      a.out[pix] = acc[0] + a.bias[0] + a.base[pix];
+  const int xl = threadIdx.x & 31;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int co = 8 * g + 4 * h;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = acc[4 * g + i];
+    if constexpr (MODE == kFwd) {
+      const float4 bv = *reinterpret_cast<const float4*>(sbias + co);
+      v[0] = fmaxf(v[0] + bv.x, 0.0f);
+      v[1] = fmaxf(v[1] + bv.y, 0.0f);
+      v[2] = fmaxf(v[2] + bv.z, 0.0f);
+      v[3] = fmaxf(v[3] + bv.w, 0.0f);
     }
-  } else {
-    const int xl = threadIdx.x & 31;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int co = 8 * g + 4 * h;
-      float v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = acc[4 * g + i];
-      if constexpr (MODE == kFwd) {
-        const float4 bv = *reinterpret_cast<const float4*>(sbias + co);
-        v[0] = fmaxf(v[0] + bv.x, 0.0f);
-        v[1] = fmaxf(v[1] + bv.y, 0.0f);
-        v[2] = fmaxf(v[2] + bv.z, 0.0f);
-        v[3] = fmaxf(v[3] + bv.w, 0.0f);
-      }
-      u32x2 st;
-      st[0] = f2bf2(v[0], v[1]);
-      st[1] = f2bf2(v[2], v[3]);
-      *reinterpret_cast<u32x2*>(ob + xl * kConvPitch + co) = st;
-    }
-    // the tile is private to the wave and LDS operations of a wave complete
-    // in order; the barrier only keeps the compiler from reordering
-    __builtin_amdgcn_wave_barrier();
-    const int lane = threadIdx.x & 63;
-    const long long row = img_off + (long long)o * a.W;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int p = 16 * k + (lane >> 2), c = lane & 3;
-      u32x4 v = *reinterpret_cast<const u32x4*>(ob + p * kConvPitch + 8 * c);
-      if (xw + p < a.W) {
-        const long long pix = row + xw + p;
-        if constexpr (MODE == kDgrad) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (!bf_positive(mk[k][j] & 0xffffu)) v[j] &= 0xffff0000u;
-            if (!bf_positive(mk[k][j] >> 16)) v[j] &= 0x0000ffffu;
-          }
-        }
-        *reinterpret_cast<u32x4*>(a.y + pix * 32 + 8 * c) = v;
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
+    u32x2 st;
+    st[0] = f2bf2(v[0], v[1]);
+    st[1] = f2bf2(v[2], v[3]);
+    *reinterpret_cast<u32x2*>(ob + xl * kConvPitch + co) = st;
   }
+  // the tile is private to the wave and LDS operations of a wave complete
+  // in order; the barrier only keeps the compiler from reordering
+  __builtin_amdgcn_wave_barrier();
+  const int lane = threadIdx.x & 63;
+  const long long row = img_off + (long long)o * a.W;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int p = 16 * k + (lane >> 2), c = lane & 3;
+    u32x4 v = *reinterpret_cast<const u32x4*>(ob + p * kConvPitch + 8 * c);
+    if (xw + p < a.W) {
+      const long long pix = row + xw + p;
+      if constexpr (MODE == kDgrad) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (!bf_positive(mk[k][j] & 0xffffu)) v[j] &= 0xffff0000u;
+          if (!bf_positive(mk[k][j] >> 16)) v[j] &= 0x0000ffffu;
+        }
+      }
+      *reinterpret_cast<u32x4*>(a.y + pix * 32 + 8 * c) = v;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 }
@@ -436,7 +518,7 @@ __device__ __forceinline__ void conv_row(const ConvArgs& a, const uint16_t* X, l
     if (r - 1 >= y0 && r - 1 < yend) conv_taps<2>(wa, cur, pick<(S + 1) % 3>(a0, a1, a2));
   }
   f32x16& done = pick<(S + 1) % 3>(a0, a1, a2);
-  if (emit) conv_epilogue<MODE>(a, done, img_off, o, x, h, ob, x - (threadIdx.x & 31), sbias, mk);
+  if (emit) conv_epilogue<MODE>(a, done, img_off, o, h, ob, x - (threadIdx.x & 31), sbias, mk);
   else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) done[i] = 0.0f;
@@ -963,13 +1045,13 @@ hipError_t launch_cnn_forward(const void* packed, int n, int H, int W, const flo
     a.y = A + (m + 1) * layer;
     if ((e = launch_conv32<kFwd>(a, s)) != hipSuccess) return e;
   }
-  ConvArgs a = conv_args(n, H, W);
-  a.x = A + 4 * layer;
-  a.w = reinterpret_cast<const uint16_t*>(pk + CnnPack::w6);
-  a.bias = reinterpret_cast<const float*>(pk + CnnPack::b6);
-  a.base = b;
-  a.out = u;
-  return launch_conv32<kOut>(a, s);
+  if (n > 65535) return hipErrorInvalidValue;  // grid z
+  const dim3 grid((unsigned)((4LL * W + 255) / 256), (unsigned)((H + kInRows - 1) / kInRows),
+                  (unsigned)n);
+  hipLaunchKernelGGL(conv_out_kernel, grid, dim3(256), 0, s, A + 4 * layer,
+                     reinterpret_cast<const uint16_t*>(pk + CnnPack::w6),
+                     reinterpret_cast<const float*>(pk + CnnPack::b6), b, u, H, W);
+  return hipGetLastError();
 }
 
 size_t cnn_backward_scratch(int n, int H, int W) {
